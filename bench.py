@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Throughput of the GE sweep on one MI355X.
+
+Workload (one "step"): a single rod of N = 2^24 interior points, r = 2,
+10^4 time levels, zero walls, u0 = sum_{k=1..16} (z_k/k^2) sin(k pi x) with
+z ~ N(0,1) from seed 2 (synthetic, generated on the host).  Inputs are
+resident in HBM before the timed region starts.  The metric is grid-point
+updates per second (one update = one interior u_i^{m+1}).
+
+Prints one JSON line.  Beside the headline value it carries
+  roofline     : the dominant kernel (the temporally blocked tile sweep)
+                 against its bound, timed with HIP events on its stream;
+  cpu_baseline : the CPU oracle (all host cores, one barrier per level) on a
+                 bounded number of levels of the same rod;
+  extra        : the depth-1 streaming sweep against HBM bandwidth, the
+                 compensated FP32 form on the same rod, and a sampled parity
+                 check of the timed result against the oracle.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GE grid-point updates/s + % HBM roofline; surrogate vs plain at 1e-4 rel L2"
+N_DEFAULT = 1 << 24
+R = 2.0
+LEVELS = 10000
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector, published
+FP32_VECTOR_TFLOPS = 157.3
+FLOPS_PER_UPDATE = {"fp64": 6, "fp32": 6, "fp32c": 12}
+BYTES_PER_POINT = {"fp64": 8, "fp32": 4, "fp32c": 8}
+
+
+def launches_per_call(cfg, n_window_fits, nsteps):
+    """Kernel launches ge_step_n issues for one call (see ge_api.hip)."""
+    if n_window_fits:
+        return (nsteps + 65535) // 65536
+    k = (nsteps + cfg["depth"] - 1) // cfg["depth"]
+    if k % 2 == 1 and nsteps > k:
+        k += 1
+    return k
+
+
+def time_runs(torch, stream, fn, warmup, steps):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ev0.elapsed_time(ev1) / 1e3
+
+
+def cpu_baseline(u0, target_s):
+    """The oracle as it stands, all host cores, on the first levels of the
+    same rod; the number of levels is chosen to take about target_s."""
+    import oracle
+    threads = os.cpu_count() or 1
+    n = u0.size
+    t = time.perf_counter()
+    oracle.step_n(u0, R, 2, nthreads=threads)
+    t2 = max(time.perf_counter() - t, 1e-3) / 2
+    levels = int(max(4, min(LEVELS, target_s / t2)))
+    t = time.perf_counter()
+    oracle.step_n(u0, R, levels, nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": n * levels / dt, "unit": "updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"same rod (N={n}), first {levels} of {LEVELS} levels, FP64 C oracle, "
+                      f"{threads} threads with a barrier per level, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c", "fp32"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the sweep of one rod runs on a single "
+              "MI355X and no multi-GPU path is built (run with --gpus 1).", file=sys.stderr)
+        return 3
+
+    import torch
+    from paper_1310_3422_amd import ge, inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 2
+
+    n = N_DEFAULT
+    prec = args.precision
+    print(f"[bench] generating rod N={n} ...", file=sys.stderr, flush=True)
+    u0 = inputs.sine_rod(n, seed=2)
+    stream = torch.cuda.Stream()   # default priority
+    plan = ge.Plan(n, R, prec)
+    cfg = plan.config()
+    u_init = ge.pack_state(u0, prec)
+    u = u_init.clone()
+    ws = plan.new_workspace()
+    torch.cuda.synchronize()
+
+    # Steps chain the level index: step k advances levels k*LEVELS ..
+    # (k+1)*LEVELS of the same rod (restarting from u0 would put a copy in the
+    # timed region).
+    calls = [0]
+
+    def step_chained():
+        plan.step_n(u, calls[0] * LEVELS, LEVELS, workspace=ws, stream=stream)
+        calls[0] += 1
+
+    print(f"[bench] {prec} config {cfg}, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    with torch.cuda.stream(stream):
+        u.copy_(u_init)
+        torch.cuda.synchronize()
+        wall, gpu_s = time_runs(torch, stream, step_chained, args.warmup, args.steps)
+    updates = n * LEVELS * args.steps
+    value = updates / wall
+    nl = launches_per_call(cfg, n <= 4 * 64 * cfg["tile"], LEVELS) * args.steps
+    kernel_s = gpu_s / nl
+    upd_per_launch = n * LEVELS / (nl / args.steps)
+    flops = FLOPS_PER_UPDATE[prec] * upd_per_launch
+    peak_tf = FP64_VECTOR_TFLOPS if prec == "fp64" else FP32_VECTOR_TFLOPS
+    achieved_tf = flops / kernel_s / 1e12
+    hbm_bytes = 2 * BYTES_PER_POINT[prec] * n      # one read + one write per launch
+    roofline = {
+        "bound": "alu", "achieved": round(achieved_tf, 3), "peak": peak_tf,
+        "unit": "TFLOP/s", "frac": round(achieved_tf / peak_tf, 4), "traffic": None,
+        "kernel": f"tile_kernel<{'double' if prec == 'fp64' else 'float'},{cfg['tile']},"
+                  f"{cfg['waves']},{'comp' if prec == 'fp32c' else 'plain'}>",
+        "depth": cfg["depth"], "launches": nl, "avg_launch_us": round(kernel_s * 1e6, 2),
+        "algorithmic_flops_per_launch": flops,
+        "hbm_gbs_algorithmic": round(hbm_bytes / kernel_s / 1e9, 1),
+        "hbm_frac_algorithmic": round(hbm_bytes / kernel_s / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32c": "f32x2-compensated"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "single rod, N=2^24 interior points, r=2.0, 10000 levels, "
+                               "zero walls, seeded 16-mode sine u0 (seed 2)",
+                   "n": n, "r": R, "levels": LEVELS, "precision": prec, **cfg},
+        "roofline": roofline,
+    }
+
+    if not args.no_extra:
+        import oracle
+        extra = {}
+        # sampled parity: one untimed step from u0, a 64-point block against
+        # the oracle on that block's dependence window
+        with torch.cuda.stream(stream):
+            u.copy_(u_init)
+            plan.step_n(u, 0, LEVELS, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        lo = n // 2 - 32
+        got = ge.unpack_state(u, n, prec)[lo:lo + 64]
+        v0 = ge.unpack_state(u_init, n, prec)
+        want = oracle.window_step_n(v0, lo, lo + 64, R, LEVELS, extended=(prec != "fp64"))
+        extra["parity_sample_rel_l2"] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        extra["parity_sample_increment_rel_l2"] = float(
+            np.linalg.norm((got - v0[lo:lo + 64]) - (want - v0[lo:lo + 64])) /
+            np.linalg.norm(want - v0[lo:lo + 64]))
+        # depth-1 streaming sweep: every level reads and writes the whole rod
+        p1 = ge.Plan(n, R, prec, depth=1)
+        u1 = u_init.clone()
+        ws1 = p1.new_workspace()
+        lv = 200
+        with torch.cuda.stream(stream):
+            torch.cuda.synchronize()
+            w1, g1 = time_runs(torch, stream,
+                               lambda: p1.step_n(u1, 0, lv, workspace=ws1, stream=stream), 1, 3)
+        bps = 2 * BYTES_PER_POINT[prec] * n * lv * 3 / g1 / 1e9
+        extra["streaming_depth1"] = {"updates_per_s": n * lv * 3 / w1,
+                                     "hbm_gbs_algorithmic": round(bps, 1),
+                                     "hbm_frac": round(bps / HBM_PEAK_GBS, 4)}
+        del u1, ws1
+        if prec == "fp64":
+            pc = ge.Plan(n, R, "fp32c")
+            uc = ge.pack_state(u0, "fp32c")
+            wsc = pc.new_workspace()
+            with torch.cuda.stream(stream):
+                torch.cuda.synchronize()
+                wc, gc = time_runs(torch, stream,
+                                   lambda: pc.step_n(uc, 0, LEVELS, workspace=wsc, stream=stream),
+                                   0, 1)
+            extra["fp32_compensated"] = {"updates_per_s": n * LEVELS / wc,
+                                         "config": pc.config()}
+        out["extra"] = extra
+
+    if not args.no_cpu:
+        print(f"[bench] CPU baseline (~{args.cpu_seconds:.0f} s) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(u0, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

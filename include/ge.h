@@ -1,0 +1,190 @@
+/*
+ * ge.h -- C ABI of libge, the MI355X (gfx950) group explicit (GE) sweep for
+ * the 1D diffusion equation u_t = u_xx.
+ *
+ * The method (Section 2 of Parand, Zafarvahedian and Hossayni, "GPU-
+ * Acceleration of Parallel Unconditionally Stable Group Explicit Finite
+ * Difference Method"): the rod [0,1] carries n interior unknowns u_1..u_n at
+ * x_i = i h, h = 1/(n+1), with wall values u_0 = g_L(t) and u_{n+1} = g_R(t).
+ * With r = tau/h^2, level m -> m+1 couples the points in two-point groups,
+ * (1,2),(3,4),... when m is even and (2,3),(4,5),... when m is odd; each
+ * group is solved in closed form by the confluence formulas Eq. (3)/(4)
+ * (denominator 1+2r) and a point left alone beside a wall takes Saul'yev
+ * scheme A, Eq. (1) (left wall) or scheme B, Eq. (2) (right wall).  The
+ * scheme is explicit and unconditionally stable for every r > 0.
+ *
+ * Conventions for every call:
+ *  - Arrays marked "device" live in GPU memory of the current HIP device;
+ *    arrays marked "host" live in host memory.  The caller owns every buffer;
+ *    the library never frees a caller buffer.
+ *  - State layout: the n interior values u_1..u_n, contiguous, element type
+ *    double (GE_FP64) or float (GE_FP32).  GE_FP32_COMP holds the
+ *    compensated pair (s, e), value s + e, as floats: s_1..s_n at element
+ *    offset 0 and e_1..e_n at element offset ge_comp_offset(n) (n rounded up
+ *    to a multiple of 64), 2*ge_comp_offset(n) floats in all.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *    void*, NULL = the default stream); the call returns once it is enqueued.
+ *  - Errors are returned as ge_status; on any status other than GE_OK no work
+ *    has been enqueued (GE_ERR_HIP excepted: a launch error may follow work
+ *    already enqueued by the same call).  ge_last_error() gives a message for
+ *    the last failing call of the calling thread.
+ *  - Results are bit-for-bit reproducible: they do not depend on the tiling,
+ *    the number of levels fused per launch, the grid, or how a run is split
+ *    into calls.
+ */
+#ifndef GE_H
+#define GE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GE_OK = 0,
+    GE_ERR_INVALID = 1,      /* an argument is out of range or inconsistent */
+    GE_ERR_NOMEM = 2,        /* a host or plan-time device allocation failed */
+    GE_ERR_HIP = 3,          /* the HIP runtime reported an error            */
+    GE_ERR_UNSUPPORTED = 4,  /* valid request this build does not handle     */
+    GE_ERR_NONFINITE = 5     /* a parameter or value is NaN or infinite      */
+} ge_status;
+
+typedef enum {
+    GE_FP64 = 0,       /* double state, double arithmetic                      */
+    GE_FP32 = 1,       /* float state, float arithmetic                        */
+    GE_FP32_COMP = 2   /* float pair (s, e): the increment of each level is    */
+                       /* formed from s + e and added with Kahan compensation  */
+} ge_precision;
+
+/* Library version, "major.minor.patch". */
+const char *ge_version(void);
+
+/* Message for the last failing call on the calling thread ("" if none). */
+const char *ge_last_error(void);
+
+/* Fixed name of a status code. */
+const char *ge_status_str(int status);
+
+/* Element offset of the e block of a GE_FP32_COMP state of n points
+ * (n rounded up to a multiple of 64); -1 for n < 0. */
+int64_t ge_comp_offset(int64_t n);
+
+/* ------------------------------------------------------------------------
+ * Single rod.
+ *
+ * A plan fixes the problem of Section 2 for one rod: n, r, the precision,
+ * the default (constant) wall values and, optionally, a source
+ * f(x, t) = a(t) b(x) whose profile b(x_i) is given here and whose time
+ * factor a is given per call.  A plan holds host-side metadata only.
+ * ---------------------------------------------------------------------- */
+typedef struct ge_plan_s *ge_plan_t;
+
+typedef struct {
+    int64_t n;          /* interior points, n >= 1                            */
+    double r;           /* mesh ratio tau/h^2, finite and > 0                 */
+    int32_t precision;  /* ge_precision                                       */
+    int32_t tile;       /* points per lane (even; 0 = the library's choice)   */
+    int32_t depth;      /* levels fused per launch (>= 1; 0 = library choice) */
+    int32_t waves;      /* waves per workgroup (1 or 4; 0 = library choice)   */
+    double g_left;      /* wall value g_L, used when a call gives no array    */
+    double g_right;     /* wall value g_R, likewise                           */
+    const void *src_b;  /* device, n values of the state's element type       */
+                        /* (float for both FP32 forms): b(x_i); NULL = no     */
+                        /* source.  Must stay valid while the plan is used.   */
+} ge_desc;
+
+/* Bytes of device workspace a ge_step_n call on this problem needs (the
+ * second level buffer, the size of the state): 8n for GE_FP64, 4n for
+ * GE_FP32, 8*ge_comp_offset(n) for GE_FP32_COMP.  Returns 0 for an invalid
+ * descriptor.  A rod that fits one workgroup window is advanced in place
+ * and ignores the workspace (it may then be NULL). */
+size_t ge_workspace_bytes(const ge_desc *desc);
+
+/* Validate `desc` and create a plan in *out.  Errors: GE_ERR_INVALID (null
+ * pointer, n < 1, r <= 0, unknown precision, tile/depth/waves out of range),
+ * GE_ERR_NONFINITE (r, g_left or g_right not finite), GE_ERR_NOMEM. */
+ge_status ge_plan(ge_plan_t *out, const ge_desc *desc);
+
+/* Release a plan (NULL is ignored).  Work already enqueued is unaffected. */
+void ge_destroy(ge_plan_t plan);
+
+/* Advance the state `u` (device, layout above) from global level `step0` to
+ * level step0 + nsteps.  The parity of each level, hence its grouping, is
+ * taken from the global level index, so consecutive calls compose exactly:
+ * (step0=0, nsteps=a) then (step0=a, nsteps=b) equals (0, a+b) bit for bit.
+ *
+ * workspace: device, ge_workspace_bytes(desc) bytes, 256-byte aligned, not
+ *            overlapping u; its contents on return are unspecified.
+ * g_left_t, g_right_t: device, nsteps+1 doubles each, the wall values
+ *            g(t_m) for m = step0..step0+nsteps; NULL = the plan's constant.
+ * src_a_t:   device, nsteps doubles, a(t_m + tau/2) for m = step0..; must be
+ *            given when the plan has a source and be NULL otherwise.
+ * flux:      device, 2 doubles or NULL.  Adds, level by level in FP64, the
+ *            wall first differences tau*(u_1 - g_L)/h and tau*(u_n - g_R)/h
+ *            at every new level to flux[0] and flux[1].
+ * u and workspace must be 16-byte aligned.  nsteps = 0 enqueues nothing.
+ * Errors: GE_ERR_INVALID (null plan/u/workspace, negative step0 or nsteps,
+ * misalignment, aliasing, source array missing or unexpected), GE_ERR_HIP. */
+ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0,
+                    int64_t nsteps, const double *g_left_t,
+                    const double *g_right_t, const double *src_a_t,
+                    double *flux, void *stream);
+
+/* Choice the plan made (or was given): points per lane, levels per launch,
+ * waves per workgroup, and the halo width it implies. */
+ge_status ge_plan_config(ge_plan_t plan, int32_t *tile, int32_t *depth,
+                         int32_t *waves, int32_t *halo);
+
+/* Convert between the compensated pair and FP64 (checkpoints of a
+ * GE_FP32_COMP run).  pair: device, GE_FP32_COMP layout of n points; x:
+ * device, n doubles.  to_fp64 writes x = s + e; from_fp64 writes
+ * s = fl32(x), e = fl32(x - s). */
+ge_status ge_comp_to_fp64(const float *pair, double *x, int64_t n, void *stream);
+ge_status ge_comp_from_fp64(const double *x, float *pair, int64_t n, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batch of independent rods (same scheme, each rod with its own n, r and
+ * constant walls) advanced by the same number of levels in one persistent
+ * launch.  Rod i occupies u[offsets[i] .. offsets[i] + n[i]) (in elements;
+ * GE_FP32_COMP stores the s block of every rod first, then the e block at
+ * the same offsets shifted by offsets[nrods]).  offsets[i] must be a
+ * multiple of 4 and offsets[i+1] >= offsets[i] + n[i].
+ * ---------------------------------------------------------------------- */
+typedef struct ge_batch_s *ge_batch_t;
+
+typedef struct {
+    int64_t nrods;
+    const int64_t *n;        /* host, nrods: interior points of each rod      */
+    const int64_t *offsets;  /* host, nrods+1: element offset of each rod     */
+    const double *r;         /* host, nrods: mesh ratio of each rod           */
+    const double *g_left;    /* host, nrods: constant left wall values        */
+    const double *g_right;   /* host, nrods: constant right wall values       */
+    int32_t precision;       /* GE_FP32 or GE_FP64 (GE_FP32_COMP: see above)  */
+    int32_t tune;            /* 0 = use the tuned/cached choice, 1 = re-tune  */
+} ge_batch_desc;
+
+/* Create a batch plan.  Copies the rod table to device memory the plan
+ * owns (the only device allocation the library makes; freed by
+ * ge_batch_destroy).  Errors: GE_ERR_INVALID, GE_ERR_NONFINITE,
+ * GE_ERR_UNSUPPORTED (a rod too long for the on-chip kernel), GE_ERR_NOMEM,
+ * GE_ERR_HIP. */
+ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *desc);
+void ge_batch_destroy(ge_batch_t batch);
+
+/* Bytes of device workspace ge_solve_batch needs. */
+size_t ge_batch_workspace_bytes(ge_batch_t batch);
+
+/* Advance every rod from level step0 by nsteps levels, in place in `u`
+ * (device, packed as described above), in one persistent launch that pulls
+ * rods from a queue, largest first.  workspace: device,
+ * ge_batch_workspace_bytes() bytes, 256-byte aligned. */
+ge_status ge_solve_batch(ge_batch_t batch, void *u, void *workspace,
+                         int64_t step0, int64_t nsteps, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GE_H */

@@ -1,0 +1,331 @@
+// C ABI of libge (declared in include/ge.h): argument validation, the choice
+// of tiling and temporal depth, and the launch sequence of a run.
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ge.h"
+#include "ge_kernels.h"
+
+namespace ge {
+
+int64_t comp_offset(int64_t n) { return (n + 63) / 64 * 64; }
+
+}  // namespace ge
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ge_status fail(ge_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+ge_status fail(ge_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+ge_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(GE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int elem_bytes(int prec) { return prec == ge::kFP64 ? 8 : 4; }
+
+// elements of one level buffer (the compensated pair stores two blocks)
+int64_t state_elems(int prec, int64_t n)
+{
+    return prec == ge::kFP32C ? 2 * ge::comp_offset(n) : n;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct ge_plan_s {
+    int64_t n;
+    double r;
+    int prec;
+    int tile;      // points per lane
+    int waves;     // waves per workgroup
+    int depth;     // levels per launch (multi-tile mode)
+    int halo;      // window points each side of a tile's core
+    int64_t window;
+    int64_t core;
+    int64_t ntiles;
+    bool single;   // the whole rod fits one window: no halo, all levels per launch
+    double g_left, g_right;
+    const void *src_b;
+    double c1, c2, cs, e1, e2, es, tau, h;
+};
+
+extern "C" {
+
+const char *ge_version(void) { return "0.1.0"; }
+
+const char *ge_last_error(void) { return g_last_error.c_str(); }
+
+const char *ge_status_str(int status)
+{
+    switch (status) {
+    case GE_OK: return "GE_OK";
+    case GE_ERR_INVALID: return "GE_ERR_INVALID";
+    case GE_ERR_NOMEM: return "GE_ERR_NOMEM";
+    case GE_ERR_HIP: return "GE_ERR_HIP";
+    case GE_ERR_UNSUPPORTED: return "GE_ERR_UNSUPPORTED";
+    case GE_ERR_NONFINITE: return "GE_ERR_NONFINITE";
+    default: return "GE_ERR_UNKNOWN";
+    }
+}
+
+int64_t ge_comp_offset(int64_t n) { return n < 0 ? -1 : ge::comp_offset(n); }
+
+size_t ge_workspace_bytes(const ge_desc *d)
+{
+    if (!d || d->n < 1 || d->precision < GE_FP64 || d->precision > GE_FP32_COMP)
+        return 0;
+    return (size_t)state_elems(d->precision, d->n) * (size_t)elem_bytes(d->precision);
+}
+
+ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
+{
+    if (!out)
+        return fail(GE_ERR_INVALID, "ge_plan: out is NULL");
+    *out = nullptr;
+    if (!d)
+        return fail(GE_ERR_INVALID, "ge_plan: desc is NULL");
+    if (d->n < 1)
+        return fail(GE_ERR_INVALID, "ge_plan: n = %lld, need n >= 1", (long long)d->n);
+    if (d->precision < GE_FP64 || d->precision > GE_FP32_COMP)
+        return fail(GE_ERR_INVALID, "ge_plan: unknown precision %d", d->precision);
+    if (!std::isfinite(d->r) || !std::isfinite(d->g_left) || !std::isfinite(d->g_right))
+        return fail(GE_ERR_NONFINITE, "ge_plan: r and the wall values must be finite");
+    if (!(d->r > 0.0))
+        return fail(GE_ERR_INVALID, "ge_plan: r = %g, need r > 0", d->r);
+    if (d->src_b && !aligned16(d->src_b))
+        return fail(GE_ERR_INVALID, "ge_plan: src_b must be 16-byte aligned");
+
+    const int prec = d->precision;
+    int tile = d->tile, waves = d->waves, depth = d->depth;
+    if (tile == 0) tile = (prec == ge::kFP32) ? 32 : 16;
+    if (waves == 0) waves = 4;
+    if (depth == 0) depth = 32;
+    if (depth < 1)
+        return fail(GE_ERR_INVALID, "ge_plan: depth = %d, need depth >= 1", depth);
+    if (!ge::tile_config_supported(prec, tile, waves))
+        return fail(GE_ERR_INVALID, "ge_plan: tile %d with %d waves is not built for precision %d",
+                    tile, waves, prec);
+
+    ge_plan_s *p = new (std::nothrow) ge_plan_s();
+    if (!p)
+        return fail(GE_ERR_NOMEM, "ge_plan: out of host memory");
+    p->n = d->n;
+    p->r = d->r;
+    p->prec = prec;
+    p->tile = tile;
+    p->waves = waves;
+    p->window = (int64_t)waves * 64 * tile;
+    p->g_left = d->g_left;
+    p->g_right = d->g_right;
+    p->src_b = d->src_b;
+    const int align = (prec == ge::kFP64) ? 2 : 4;   // values per 16-byte chunk
+    if (p->n <= p->window) {
+        // One window holds the rod and both walls: nothing enters from an
+        // open edge, so every level of a call runs in one in-place launch.
+        p->single = true;
+        p->depth = depth;
+        p->halo = 0;
+        p->core = p->window;
+        p->ntiles = 1;
+    } else {
+        p->single = false;
+        p->depth = depth;
+        p->halo = (int)round_up(depth + 1, align);
+        p->core = p->window - 2 * p->halo;
+        if (p->core < p->window / 2) {
+            delete p;
+            return fail(GE_ERR_INVALID,
+                        "ge_plan: depth %d needs a halo of %d, too wide for a %lld-point window",
+                        depth, (int)round_up(depth + 1, align), (long long)(waves * 64 * tile));
+        }
+        p->ntiles = (p->n + p->core - 1) / p->core;
+    }
+    const double r = p->r;
+    p->h = 1.0 / (double)(p->n + 1);
+    p->tau = r * p->h * p->h;
+    p->c1 = (r + r * r) / (1.0 + 2.0 * r);
+    p->c2 = (r * r) / (1.0 + 2.0 * r);
+    p->cs = r / (1.0 + r);
+    p->e1 = p->tau * (1.0 + r) / (1.0 + 2.0 * r);
+    p->e2 = p->tau * r / (1.0 + 2.0 * r);
+    p->es = p->tau / (1.0 + r);
+    *out = p;
+    return GE_OK;
+}
+
+void ge_destroy(ge_plan_t plan) { delete plan; }
+
+ge_status ge_plan_config(ge_plan_t plan, int32_t *tile, int32_t *depth, int32_t *waves,
+                         int32_t *halo)
+{
+    if (!plan)
+        return fail(GE_ERR_INVALID, "ge_plan_config: plan is NULL");
+    if (tile) *tile = plan->tile;
+    if (depth) *depth = plan->depth;
+    if (waves) *waves = plan->waves;
+    if (halo) *halo = plan->halo;
+    return GE_OK;
+}
+
+ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int64_t nsteps,
+                    const double *g_left_t, const double *g_right_t, const double *src_a_t,
+                    double *flux, void *stream)
+{
+    if (!plan)
+        return fail(GE_ERR_INVALID, "ge_step_n: plan is NULL");
+    if (!u)
+        return fail(GE_ERR_INVALID, "ge_step_n: u is NULL");
+    if (step0 < 0 || nsteps < 0)
+        return fail(GE_ERR_INVALID, "ge_step_n: step0 and nsteps must be >= 0");
+    if (!aligned16(u))
+        return fail(GE_ERR_INVALID, "ge_step_n: u must be 16-byte aligned");
+    if ((plan->src_b != nullptr) != (src_a_t != nullptr))
+        return fail(GE_ERR_INVALID, plan->src_b ? "ge_step_n: the plan has a source, src_a_t is NULL"
+                                                : "ge_step_n: src_a_t given but the plan has no source");
+    const size_t bytes = (size_t)state_elems(plan->prec, plan->n) * elem_bytes(plan->prec);
+    if (!plan->single) {
+        if (!workspace)
+            return fail(GE_ERR_INVALID, "ge_step_n: workspace is NULL");
+        if (!aligned16(workspace))
+            return fail(GE_ERR_INVALID, "ge_step_n: workspace must be 16-byte aligned");
+        const uintptr_t a0 = (uintptr_t)u, a1 = a0 + bytes;
+        const uintptr_t b0 = (uintptr_t)workspace, b1 = b0 + bytes;
+        if (a0 < b1 && b0 < a1)
+            return fail(GE_ERR_INVALID, "ge_step_n: u and workspace overlap");
+    }
+    if (nsteps == 0)
+        return GE_OK;
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ge::TileArgs a{};
+    a.src_b = plan->src_b;
+    a.flux = flux;
+    a.n = plan->n;
+    a.core = plan->core;
+    a.ntiles = plan->ntiles;
+    a.halo = plan->halo;
+    a.estride = plan->prec == ge::kFP32C ? ge::comp_offset(plan->n) : 0;
+    a.c1 = plan->c1; a.c2 = plan->c2; a.cs = plan->cs;
+    a.e1 = plan->e1; a.e2 = plan->e2; a.es = plan->es;
+    a.gl0 = plan->g_left; a.gr0 = plan->g_right;
+    a.tau = plan->tau; a.h = plan->h;
+    const bool src = plan->src_b != nullptr;
+
+    if (plan->single) {
+        // in place, bounded work per launch
+        const int64_t chunk = 1 << 16;
+        for (int64_t done = 0; done < nsteps; done += chunk) {
+            const int64_t lev = (nsteps - done < chunk) ? nsteps - done : chunk;
+            a.in = u;
+            a.out = u;
+            a.level0 = step0 + done;
+            a.nlev = (int32_t)lev;
+            a.gl_t = g_left_t ? g_left_t + done : nullptr;
+            a.gr_t = g_right_t ? g_right_t + done : nullptr;
+            a.src_a = src_a_t ? src_a_t + done : nullptr;
+            hipError_t e = ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, a, st);
+            if (e != hipSuccess)
+                return hip_fail(e, "ge_step_n: launch");
+        }
+        return GE_OK;
+    }
+
+    // Ping-pong between u and the workspace.  An even number of launches
+    // leaves the result in u; the levels are spread evenly over them.
+    int64_t launches = (nsteps + plan->depth - 1) / plan->depth;
+    if ((launches & 1) && nsteps > launches)
+        ++launches;
+    const int64_t base = nsteps / launches, extra = nsteps % launches;
+    void *bufs[2] = {u, workspace};
+    int64_t done = 0;
+    for (int64_t k = 0; k < launches; ++k) {
+        const int64_t lev = base + (k < extra ? 1 : 0);
+        a.in = bufs[k & 1];
+        a.out = bufs[(k + 1) & 1];
+        a.level0 = step0 + done;
+        a.nlev = (int32_t)lev;
+        a.gl_t = g_left_t ? g_left_t + done : nullptr;
+        a.gr_t = g_right_t ? g_right_t + done : nullptr;
+        a.src_a = src_a_t ? src_a_t + done : nullptr;
+        hipError_t e = ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, a, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "ge_step_n: launch");
+        done += lev;
+    }
+    if (launches & 1) {
+        hipError_t e = hipMemcpyAsync(u, workspace, bytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess)
+            return hip_fail(e, "ge_step_n: copy back");
+    }
+    return GE_OK;
+}
+
+ge_status ge_comp_to_fp64(const float *pair, double *x, int64_t n, void *stream)
+{
+    if (!pair || !x || n < 0)
+        return fail(GE_ERR_INVALID, "ge_comp_to_fp64: bad arguments");
+    hipError_t e = ge::launch_comp_to_fp64(pair, x, n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GE_OK : hip_fail(e, "ge_comp_to_fp64");
+}
+
+ge_status ge_comp_from_fp64(const double *x, float *pair, int64_t n, void *stream)
+{
+    if (!pair || !x || n < 0)
+        return fail(GE_ERR_INVALID, "ge_comp_from_fp64: bad arguments");
+    hipError_t e = ge::launch_comp_from_fp64(x, pair, n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GE_OK : hip_fail(e, "ge_comp_from_fp64");
+}
+
+}  // extern "C"
+
+// ---- batch of rods (not built yet) ---------------------------------------
+struct ge_batch_s {
+    int64_t nrods;
+};
+
+extern "C" {
+
+ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *desc)
+{
+    if (out) *out = nullptr;
+    (void)desc;
+    return fail(GE_ERR_UNSUPPORTED, "ge_batch_plan: not available in this build");
+}
+
+void ge_batch_destroy(ge_batch_t batch) { delete batch; }
+
+size_t ge_batch_workspace_bytes(ge_batch_t batch)
+{
+    (void)batch;
+    return 0;
+}
+
+ge_status ge_solve_batch(ge_batch_t batch, void *u, void *workspace, int64_t step0,
+                         int64_t nsteps, void *stream)
+{
+    (void)batch; (void)u; (void)workspace; (void)step0; (void)nsteps; (void)stream;
+    return fail(GE_ERR_UNSUPPORTED, "ge_solve_batch: not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,231 @@
+"""Thin ctypes binding of libge (include/ge.h).
+
+The C functions keep their names (``ge_plan``, ``ge_step_n``, ...); the
+classes below only marshal torch tensors (device memory) and torch streams
+into plain pointers.  Every level of the sweep runs in the HIP kernels of
+libge.so; there is no fallback path, and a missing library raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libge.so")
+
+GE_OK, GE_ERR_INVALID, GE_ERR_NOMEM, GE_ERR_HIP, GE_ERR_UNSUPPORTED, GE_ERR_NONFINITE = range(6)
+GE_FP64, GE_FP32, GE_FP32_COMP = 0, 1, 2
+PRECISIONS = {"fp64": GE_FP64, "fp32": GE_FP32, "fp32c": GE_FP32_COMP}
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+
+
+class GeDesc(ctypes.Structure):
+    _fields_ = [("n", _i64), ("r", _dbl), ("precision", _i32), ("tile", _i32),
+                ("depth", _i32), ("waves", _i32), ("g_left", _dbl),
+                ("g_right", _dbl), ("src_b", _vp)]
+
+
+class GeBatchDesc(ctypes.Structure):
+    _fields_ = [("nrods", _i64), ("n", _vp), ("offsets", _vp), ("r", _vp),
+                ("g_left", _vp), ("g_right", _vp), ("precision", _i32),
+                ("tune", _i32)]
+
+
+class GEError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_str(status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "ge_version": (ctypes.c_char_p, []),
+    "ge_last_error": (ctypes.c_char_p, []),
+    "ge_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "ge_comp_offset": (_i64, [_i64]),
+    "ge_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(GeDesc)]),
+    "ge_plan": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GeDesc)]),
+    "ge_destroy": (None, [_vp]),
+    "ge_step_n": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "ge_plan_config": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "ge_comp_to_fp64": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
+    "ge_comp_from_fp64": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
+    "ge_batch_plan": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GeBatchDesc)]),
+    "ge_batch_destroy": (None, [_vp]),
+    "ge_batch_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "ge_solve_batch": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
+}
+
+
+def lib():
+    """Load libge.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1310_3422_amd.build`")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def status_str(status):
+    return lib().ge_status_str(status).decode()
+
+
+def last_error():
+    return lib().ge_last_error().decode()
+
+
+def check(status):
+    if status != GE_OK:
+        raise GEError(status, last_error())
+
+
+def comp_offset(n):
+    return int(lib().ge_comp_offset(n))
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def state_dtype(precision):
+    torch = _torch()
+    return torch.float64 if _prec(precision) == GE_FP64 else torch.float32
+
+
+def state_numel(n, precision):
+    return 2 * comp_offset(n) if _prec(precision) == GE_FP32_COMP else n
+
+
+class Plan:
+    """A ge_plan for one rod; ``step_n`` advances a device state tensor."""
+
+    def __init__(self, n, r, precision="fp64", g_left=0.0, g_right=0.0, src_b=None,
+                 tile=0, depth=0, waves=0):
+        self.n, self.r = int(n), float(r)
+        self.precision = _prec(precision)
+        self._src_b = src_b   # keep the profile alive
+        if src_b is not None:
+            self._check_tensor(src_b, self.n, "src_b", state_dtype(self.precision))
+        self.desc = GeDesc(n=self.n, r=self.r, precision=self.precision, tile=tile,
+                           depth=depth, waves=waves, g_left=float(g_left),
+                           g_right=float(g_right), src_b=_ptr(src_b))
+        h = _vp()
+        check(lib().ge_plan(ctypes.byref(h), ctypes.byref(self.desc)))
+        self.handle = h
+        self.workspace_bytes = int(lib().ge_workspace_bytes(ctypes.byref(self.desc)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.ge_destroy(h)
+            self.handle = None
+
+    def config(self):
+        t, d, w, h = _i32(), _i32(), _i32(), _i32()
+        check(lib().ge_plan_config(self.handle, ctypes.byref(t), ctypes.byref(d),
+                                   ctypes.byref(w), ctypes.byref(h)))
+        return {"tile": t.value, "depth": d.value, "waves": w.value, "halo": h.value}
+
+    @staticmethod
+    def _check_tensor(t, numel, name, dtype):
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of {numel} values")
+
+    def new_state(self):
+        torch = _torch()
+        return torch.zeros(state_numel(self.n, self.precision),
+                           dtype=state_dtype(self.precision), device="cuda")
+
+    def new_workspace(self):
+        torch = _torch()
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+
+    def step_n(self, u, step0, nsteps, workspace=None, g_left_t=None, g_right_t=None,
+               src_a_t=None, flux=None, stream=None):
+        torch = _torch()
+        self._check_tensor(u, state_numel(self.n, self.precision), "u",
+                           state_dtype(self.precision))
+        if workspace is None:
+            workspace = self.new_workspace()
+        for name, t, k in (("g_left_t", g_left_t, nsteps + 1), ("g_right_t", g_right_t, nsteps + 1),
+                           ("src_a_t", src_a_t, nsteps), ("flux", flux, 2)):
+            if t is not None:
+                self._check_tensor(t, k, name, torch.float64)
+        check(lib().ge_step_n(self.handle, _ptr(u), _ptr(workspace), int(step0), int(nsteps),
+                              _ptr(g_left_t), _ptr(g_right_t), _ptr(src_a_t), _ptr(flux),
+                              _stream_ptr(stream)))
+        return u
+
+
+def comp_to_fp64(pair, n, stream=None):
+    torch = _torch()
+    x = torch.empty(n, dtype=torch.float64, device=pair.device)
+    check(lib().ge_comp_to_fp64(_ptr(pair), _ptr(x), int(n), _stream_ptr(stream)))
+    return x
+
+
+def comp_from_fp64(x, stream=None):
+    torch = _torch()
+    n = x.numel()
+    pair = torch.zeros(2 * comp_offset(n), dtype=torch.float32, device=x.device)
+    check(lib().ge_comp_from_fp64(_ptr(x), _ptr(pair), int(n), _stream_ptr(stream)))
+    return pair
+
+
+def pack_state(u0, precision, device="cuda"):
+    """Host FP64 values -> device state tensor in the precision's layout
+    (FP32 forms round the same FP64 values; the compensated pair starts with
+    e = fl32(u0 - s))."""
+    torch = _torch()
+    p = _prec(precision)
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    if p == GE_FP64:
+        return torch.from_numpy(u0.copy()).to(device)
+    if p == GE_FP32:
+        return torch.from_numpy(u0.astype(np.float32)).to(device)
+    n = u0.size
+    off = comp_offset(n)
+    s = u0.astype(np.float32)
+    e = (u0 - s.astype(np.float64)).astype(np.float32)
+    buf = np.zeros(2 * off, dtype=np.float32)
+    buf[:n], buf[off:off + n] = s, e
+    return torch.from_numpy(buf).to(device)
+
+
+def unpack_state(u, n, precision):
+    """Device state tensor -> host FP64 values (s + e for the pair)."""
+    p = _prec(precision)
+    a = u.detach().cpu().numpy()
+    if p == GE_FP32_COMP:
+        off = comp_offset(n)
+        return a[:n].astype(np.float64) + a[off:off + n].astype(np.float64)
+    return a[:n].astype(np.float64)

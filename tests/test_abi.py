@@ -1,0 +1,162 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/ge.h declares, and validates its arguments without touching a GPU
+(every call here returns before any work would be enqueued)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1310_3422_amd import ge
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.skipif(not os.path.exists(ge.LIB_PATH),
+                                reason="libge.so not built")
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(ge_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "ge_step_n" in names and "ge_plan" in names and "ge_solve_batch" in names
+    h = ctypes.CDLL(ge.LIB_PATH)
+    missing = [n for n in names if not hasattr(h, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version():
+    assert ge.status_str(0) == "GE_OK"
+    assert ge.status_str(5) == "GE_ERR_NONFINITE"
+    assert ge.lib().ge_version().decode().count(".") == 2
+
+
+def _plan(**kw):
+    d = dict(n=1000, r=1.0, precision=0, tile=0, depth=0, waves=0, g_left=0.0,
+             g_right=0.0, src_b=None)
+    d.update(kw)
+    desc = ge.GeDesc(**d)
+    h = ctypes.c_void_p()
+    st = ge.lib().ge_plan(ctypes.byref(h), ctypes.byref(desc))
+    return st, h
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=0), ge.GE_ERR_INVALID),
+    (dict(n=-5), ge.GE_ERR_INVALID),
+    (dict(r=0.0), ge.GE_ERR_INVALID),
+    (dict(r=-1.0), ge.GE_ERR_INVALID),
+    (dict(r=float("nan")), ge.GE_ERR_NONFINITE),
+    (dict(r=float("inf")), ge.GE_ERR_NONFINITE),
+    (dict(g_left=float("nan")), ge.GE_ERR_NONFINITE),
+    (dict(precision=7), ge.GE_ERR_INVALID),
+    (dict(tile=6), ge.GE_ERR_INVALID),
+    (dict(waves=3), ge.GE_ERR_INVALID),
+    (dict(depth=-2), ge.GE_ERR_INVALID),
+    (dict(n=10 ** 6, tile=8, waves=1, depth=200), ge.GE_ERR_INVALID),
+    (dict(src_b=ctypes.c_void_p(0x1004)), ge.GE_ERR_INVALID),
+])
+def test_plan_rejects(kw, status):
+    st, h = _plan(**kw)
+    assert st == status
+    assert not h.value
+    assert ge.last_error()
+
+
+def test_null_arguments():
+    lib = ge.lib()
+    assert lib.ge_plan(None, None) == ge.GE_ERR_INVALID
+    h = ctypes.c_void_p()
+    assert lib.ge_plan(ctypes.byref(h), None) == ge.GE_ERR_INVALID
+    assert lib.ge_step_n(None, None, None, 0, 1, None, None, None, None, None) == ge.GE_ERR_INVALID
+    lib.ge_destroy(None)
+
+
+@pytest.mark.parametrize("prec,depth", [(0, 1), (0, 32), (1, 7), (2, 33)])
+def test_plan_config_halo_rule(prec, depth):
+    st, h = _plan(n=10 ** 6, precision=prec, depth=depth)
+    assert st == ge.GE_OK
+    t, d, w, hal = (ctypes.c_int32() for _ in range(4))
+    assert ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w),
+                                   ctypes.byref(hal)) == ge.GE_OK
+    align = 2 if prec == 0 else 4
+    assert d.value == depth
+    assert hal.value == (depth + 1 + align - 1) // align * align
+    ge.lib().ge_destroy(h)
+
+
+def test_single_window_rod_needs_no_halo():
+    st, h = _plan(n=1024, precision=0, tile=16, waves=4)
+    assert st == ge.GE_OK
+    hal = ctypes.c_int32()
+    ge.lib().ge_plan_config(h, None, None, None, ctypes.byref(hal))
+    assert hal.value == 0
+    ge.lib().ge_destroy(h)
+
+
+def test_workspace_bytes():
+    lib = ge.lib()
+    for prec, n, want in ((0, 1000, 8000), (1, 1000, 4000), (2, 1000, 8 * 1024), (2, 64, 512)):
+        desc = ge.GeDesc(n=n, r=1.0, precision=prec)
+        assert lib.ge_workspace_bytes(ctypes.byref(desc)) == want
+    assert lib.ge_workspace_bytes(None) == 0
+    assert ge.comp_offset(1) == 64 and ge.comp_offset(128) == 128 and ge.comp_offset(-1) == -1
+
+
+def test_step_n_validation_enqueues_nothing():
+    """Fake (never dereferenced) device addresses: every call below must be
+    rejected, or be a no-op, before any launch."""
+    lib = ge.lib()
+    st, h = _plan(n=10 ** 6, precision=0)
+    assert st == ge.GE_OK
+    u = ctypes.c_void_p(0x10000000)
+    ws = ctypes.c_void_p(0x20000000)
+    call = lambda *a: lib.ge_step_n(h, *a)
+    assert call(None, ws, 0, 5, None, None, None, None, None) == ge.GE_ERR_INVALID
+    assert call(u, None, 0, 5, None, None, None, None, None) == ge.GE_ERR_INVALID
+    assert call(u, ws, -1, 5, None, None, None, None, None) == ge.GE_ERR_INVALID
+    assert call(u, ws, 0, -5, None, None, None, None, None) == ge.GE_ERR_INVALID
+    assert call(ctypes.c_void_p(0x10000008), ws, 0, 5, None, None, None, None, None) == ge.GE_ERR_INVALID
+    assert call(u, ctypes.c_void_p(0x20000004), 0, 5, None, None, None, None, None) == ge.GE_ERR_INVALID
+    # overlapping buffers
+    assert call(u, ctypes.c_void_p(0x10000000 + 8 * 1000), 0, 5, None, None, None, None,
+                None) == ge.GE_ERR_INVALID
+    # a source array without a source profile
+    assert call(u, ws, 0, 5, None, None, ctypes.c_void_p(0x30000000), None, None) == ge.GE_ERR_INVALID
+    # nothing to do
+    assert call(u, ws, 0, 0, None, None, None, None, None) == ge.GE_OK
+    lib.ge_destroy(h)
+
+
+@pytest.mark.parametrize("depth", list(range(1, 17)))
+@pytest.mark.parametrize("step0", [0, 1])
+def test_halo_of_depth_plus_one_is_enough_and_tight(depth, step0):
+    """The library recomputes a halo of depth+1 points (rounded up) on each
+    side of a tile instead of exchanging it.  On the oracle: cutting a rod at
+    an even index and feeding garbage in at the cut leaves every point more
+    than depth+1 away from the cut exact after `depth` levels."""
+    rng = np.random.default_rng(depth)
+    n = 200
+    u = rng.standard_normal(n)
+    full = oracle.step_n(u, 2.5, depth, step0=step0)
+    a, b = 60, 140
+    h = 1.0 / (n + 1)
+    cut = oracle.step_n(u[a:b], 2.5, depth, step0=step0, gl=1e3, gr=-1e3, tau=2.5 * h * h, h=h)
+    lo, hi = depth + 1, (b - a) - depth - 1
+    np.testing.assert_array_equal(cut[lo:hi], full[a + lo:a + hi])
+    # starting on an even level the bound is reached: one point closer to
+    # either cut is contaminated (starting on an odd level depth suffices)
+    if step0 == 0:
+        assert cut[lo - 1] != full[a + lo - 1] and cut[hi] != full[a + hi]

@@ -70,10 +70,11 @@ def cpu_baseline(u0, target_s):
     import oracle
     threads = os.cpu_count() or 1
     n = u0.size
+    probe = 16
     t = time.perf_counter()
-    oracle.step_n(u0, R, 2, nthreads=threads)
-    t2 = max(time.perf_counter() - t, 1e-3) / 2
-    levels = int(max(4, min(LEVELS, target_s / t2)))
+    oracle.step_n(u0, R, probe, nthreads=threads)
+    per_level = max(time.perf_counter() - t, 1e-3) / probe
+    levels = int(max(probe, min(LEVELS, target_s / per_level)))
     t = time.perf_counter()
     oracle.step_n(u0, R, levels, nthreads=threads)
     dt = time.perf_counter() - t

@@ -15,7 +15,11 @@
 //
 // D_i is formed from first differences d_i = u_{i+1} - u_i as
 // D_i = d_i - d_{i-1}; for smooth data the differences are exact, so the
-// increment carries a relative (not absolute) rounding error.
+// increment carries a relative (not absolute) rounding error.  FP64 then
+// applies u' = fma(c2, D_q, fma(c1, D_i, u)); FP32 forms the increment
+// first and rounds u once per level.  The compensated FP32 pair (s, e),
+// value s + e, takes D from the s and e second differences summed at the
+// end, and adds the increment with Kahan's compensated sum.
 //
 // Mapping: one workgroup of NW waves owns a window of W = NW*64*K points;
 // lane l of wave w holds points (64w + l)K .. (64w + l)K + K-1 of the window
@@ -37,29 +41,39 @@ namespace {
 
 constexpr int kWave = 64;
 
-// ---- cross-lane moves (DPP wave shifts, zero into the vacated lane) -------
-__device__ __forceinline__ int shr1_i(int v)
+// ---- cross-lane moves ------------------------------------------------------
+// DPP wave shifts by one lane; the lane with no source (lane 0 for a shift
+// right, lane 63 for a shift left) receives `fill`.
+__device__ __forceinline__ int shr1_i(int fill, int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);  // wave_shr:1
+    return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xF, 0xF, false);  // wave_shr:1
 }
-__device__ __forceinline__ int shl1_i(int v)
+__device__ __forceinline__ int shl1_i(int fill, int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true);  // wave_shl:1
+    return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xF, 0xF, false);  // wave_shl:1
 }
-// value held by lane l-1
-__device__ __forceinline__ float from_left(float v) { return __int_as_float(shr1_i(__float_as_int(v))); }
-// value held by lane l+1
-__device__ __forceinline__ float from_right(float v) { return __int_as_float(shl1_i(__float_as_int(v))); }
-__device__ __forceinline__ double from_left(double v)
+// value held by lane l-1 (lane 0: fill)
+__device__ __forceinline__ float from_left(float fill, float v)
 {
-    const long long b = __double_as_longlong(v);
-    const int lo = shr1_i((int)(b & 0xffffffffll)), hi = shr1_i((int)(b >> 32));
+    return __int_as_float(shr1_i(__float_as_int(fill), __float_as_int(v)));
+}
+// value held by lane l+1 (lane 63: fill)
+__device__ __forceinline__ float from_right(float fill, float v)
+{
+    return __int_as_float(shl1_i(__float_as_int(fill), __float_as_int(v)));
+}
+__device__ __forceinline__ double from_left(double fill, double v)
+{
+    const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
+    const int lo = shr1_i((int)(f & 0xffffffffll), (int)(b & 0xffffffffll));
+    const int hi = shr1_i((int)(f >> 32), (int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-__device__ __forceinline__ double from_right(double v)
+__device__ __forceinline__ double from_right(double fill, double v)
 {
-    const long long b = __double_as_longlong(v);
-    const int lo = shl1_i((int)(b & 0xffffffffll)), hi = shl1_i((int)(b >> 32));
+    const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
+    const int lo = shl1_i((int)(f & 0xffffffffll), (int)(b & 0xffffffffll));
+    const int hi = shl1_i((int)(f >> 32), (int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -157,6 +171,10 @@ __device__ __forceinline__ void put_at(T (&v)[K], int k, bool pred, T x)
             v[j] = pred ? x : v[j];
 }
 
+// A first difference: one value, or the (s, e) parts of the pair kept apart.
+template <typename T, bool COMP> struct Dif { T s; };
+template <typename T> struct Dif<T, true> { T s, e; };
+
 // Wall value split for the state type: (hi, lo) with hi + lo ~ g.
 template <typename T, bool COMP>
 __device__ __forceinline__ void split_wall(double g, T &hi, T &lo)
@@ -203,8 +221,8 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
     // source profile of the neighbours' edge points (fixed for the launch)
     T bl = T(0), br = T(0);
     if constexpr (SRC) {
-        bl = from_left(b[K - 1]);
-        br = from_right(b[0]);
+        bl = from_left(T(0), b[K - 1]);
+        br = from_right(T(0), b[0]);
         if constexpr (NW > 1) {
             if (lane == 0) xb[w][0] = b[0];
             if (lane == kWave - 1) xb[w][1] = b[K - 1];
@@ -249,14 +267,11 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
             }
         }
 
-        // neighbour values: u_{-2}, u_{-1} (left) and u_K, u_{K+1} (right)
-        T sl = from_left(s[K - 1]), sl2 = from_left(s[K - 2]);
-        T sr = from_right(s[0]), sr2 = from_right(s[1]);
-        T el = T(0), el2 = T(0), er = T(0), er2 = T(0);
-        if constexpr (COMP) {
-            el = from_left(e[K - 1]); el2 = from_left(e[K - 2]);
-            er = from_right(e[0]); er2 = from_right(e[1]);
-        }
+        // Values entering the wave at its edges: from the neighbouring waves
+        // through LDS, or (at an open window edge) anything -- those points
+        // lie in the halo.  They ride in as the DPP fill of lanes 0 and 63.
+        T xl = T(0), xl2 = T(0), xr = T(0), xr2 = T(0);
+        T yl = T(0), yl2 = T(0), yr = T(0), yr2 = T(0);
         if constexpr (NW > 1) {
             const int pb = lev & 1;
             if (lane == 0) { xs[pb][w][0] = s[0]; xs[pb][w][1] = s[1]; }
@@ -267,70 +282,109 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
             }
             __syncthreads();
             const int wl = w > 0 ? w - 1 : 0, wr = w < NW - 1 ? w + 1 : NW - 1;
-            const bool take_l = (lane == 0) && (w > 0);
-            const bool take_r = (lane == kWave - 1) && (w < NW - 1);
-            const T xl = xs[pb][wl][3], xl2 = xs[pb][wl][2];
-            const T xr = xs[pb][wr][0], xr2 = xs[pb][wr][1];
-            sl = take_l ? xl : sl; sl2 = take_l ? xl2 : sl2;
-            sr = take_r ? xr : sr; sr2 = take_r ? xr2 : sr2;
+            xl = xs[pb][wl][3]; xr = xs[pb][wr][0];
+            xl2 = xs[pb][wl][2]; xr2 = xs[pb][wr][1];
             if constexpr (COMP) {
-                const T yl = xe[pb][wl][3], yl2 = xe[pb][wl][2];
-                const T yr = xe[pb][wr][0], yr2 = xe[pb][wr][1];
-                el = take_l ? yl : el; el2 = take_l ? yl2 : el2;
-                er = take_r ? yr : er; er2 = take_r ? yr2 : er2;
+                yl = xe[pb][wl][3]; yr = xe[pb][wr][0];
+                yl2 = xe[pb][wl][2]; yr2 = xe[pb][wr][1];
             }
         }
         T dgl = T(0), dgr = T(0);
-        bool singL = false, singR = false, isL = false, isS = false;
+        bool isL = false, isS = false;
         if constexpr (WALL) {
-            if (left_wall && tid == 0) {
+            if (left_wall && w == 0) {
                 T gh, glw;
                 split_wall<T, COMP>(glo, gh, glw);
-                sl = gh;
-                if constexpr (COMP) el = glw;
+                xl = gh;
+                if constexpr (COMP) yl = glw;
             }
-            if (ghost_edge && tid == NW * kWave - 1) {
+            if (ghost_edge && w == NW - 1) {
                 T gh, glw;
                 split_wall<T, COMP>(gro, gh, glw);
-                sr = gh;
-                if constexpr (COMP) er = glw;
+                xr = gh;
+                if constexpr (COMP) yr = glw;
             }
             dgl = (T)(gln - glo);
             dgr = (T)(grn - gro);
-            singL = left_wall && (p == 1);
-            singR = has_S && (((n - 1 + p) & 1) == 0);
-            isL = singL && (tid == 0);
-            isS = singR && (tid == lS);
+            isL = left_wall && (p == 1) && (tid == 0);
+            isS = has_S && (((n - 1 + p) & 1) == 0) && (tid == lS);
         }
+        // u_{-1} and u_K: neighbour lanes' edge points
+        const T sl = from_left(xl, s[K - 1]), sr = from_right(xr, s[0]);
+        T el = T(0), er = T(0);
+        if constexpr (COMP) { el = from_left(yl, e[K - 1]); er = from_right(yr, e[0]); }
         const T an = SRC ? (T)a.src_a[lev] : T(0);
 
-        // first difference u_{j+1} - u_j between two points given as (s, e)
-        auto dif = [&](T s1, T e1_, T s0, T e0) -> T {
-            if constexpr (COMP) return (s1 - s0) + (e1_ - e0);
-            else return s1 - s0;
+        // First difference u_{j+1} - u_j of two points given as (s, e).  For
+        // the pair the s and e parts stay apart: for smooth data the s
+        // differences (and their differences) are exact, and summing the s
+        // and e second differences only at the end keeps D accurate to the
+        // precision of the pair.
+        auto dif = [&](T s1, T e1_, T s0, T e0) -> Dif<T, COMP> {
+            if constexpr (COMP) return Dif<T, COMP>{s1 - s0, e1_ - e0};
+            else return Dif<T, COMP>{s1 - s0};
         };
-        // advance point j by the increment built from D_self, D_partner
+        // second difference D = db - da from consecutive first differences
+        auto sd = [&](Dif<T, COMP> da, Dif<T, COMP> db) -> T {
+            if constexpr (COMP) return (db.s - da.s) + (db.e - da.e);
+            else return db.s - da.s;
+        };
+        // advance point j from D_self and D_partner (bp: partner's profile)
         auto upd = [&](int j, T Ds, T Dp, T bp) {
-            T inc = fmaT(c1, Ds, c2 * Dp);
-            if constexpr (SRC) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
-            if constexpr (WALL) {
-                if (j == kS) {
-                    T alt = cs * (Ds + dgr);
-                    if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
-                    inc = isS ? alt : inc;
-                }
-                if (j == 0) {
-                    T alt = cs * (Ds + dgl);
-                    if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
-                    inc = isL ? alt : inc;
-                }
-            }
             if constexpr (COMP) {
+                T inc = fmaT(c1, Ds, c2 * Dp);
+                if constexpr (SRC) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
+                if constexpr (WALL) {
+                    if (j == kS) {
+                        T alt = cs * (Ds + dgr);
+                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
+                        inc = isS ? alt : inc;
+                    }
+                    if (j == 0) {
+                        T alt = cs * (Ds + dgl);
+                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
+                        inc = isL ? alt : inc;
+                    }
+                }
+                // Kahan: the pair absorbs the increment, e keeps what s lost
                 const T y = inc + e[j];
                 const T tt = s[j] + y;
                 e[j] = y - (tt - s[j]);
                 s[j] = tt;
+            } else if constexpr (sizeof(T) == 8) {
+                // FP64: two fused steps, u + c1 D_self, then + c2 D_partner
+                T t = fmaT(c1, Ds, s[j]);
+                if constexpr (SRC) t = fmaT(an, fmaT(e1, b[j], e2 * bp), t);
+                T v = fmaT(c2, Dp, t);
+                if constexpr (WALL) {
+                    if (j == kS) {
+                        T alt = fmaT(cs, Ds + dgr, s[j]);
+                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
+                        v = isS ? alt : v;
+                    }
+                    if (j == 0) {
+                        T alt = fmaT(cs, Ds + dgl, s[j]);
+                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
+                        v = isL ? alt : v;
+                    }
+                }
+                s[j] = v;
             } else {
+                // FP32: form the increment first, so u is rounded once per level
+                T inc = fmaT(c1, Ds, c2 * Dp);
+                if constexpr (SRC) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
+                if constexpr (WALL) {
+                    if (j == kS) {
+                        T alt = cs * (Ds + dgr);
+                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
+                        inc = isS ? alt : inc;
+                    }
+                    if (j == 0) {
+                        T alt = cs * (Ds + dgl);
+                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
+                        inc = isL ? alt : inc;
+                    }
+                }
                 s[j] = s[j] + inc;
             }
             if constexpr (WALL) {
@@ -348,42 +402,45 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
 
         if (p == 0) {
             // pairs (2q, 2q+1) inside the lane
-            T dprev = dif(s[0], e[0], sl, el);                       // d_{-1}
+            auto dprev = dif(s[0], e[0], sl, el);                    // d_{-1}
 #pragma unroll
             for (int q = 0; q < K / 2; ++q) {
                 const int j = 2 * q;
-                const T d0 = dif(s[j + 1], e[j + 1], s[j], e[j]);    // d_j
-                const T d1 = (j + 2 < K) ? dif(s[j + 2], e[j + 2], s[j + 1], e[j + 1])
-                                         : dif(sr, er, s[j + 1], e[j + 1]);
-                const T Da = d0 - dprev, Db = d1 - d0;
+                const auto d0 = dif(s[j + 1], e[j + 1], s[j], e[j]); // d_j
+                const auto d1 = (j + 2 < K) ? dif(s[j + 2], e[j + 2], s[j + 1], e[j + 1])
+                                            : dif(sr, er, s[j + 1], e[j + 1]);
+                const T Da = sd(dprev, d0), Db = sd(d0, d1);
                 upd(j, Da, Db, b[j + 1]);
                 upd(j + 1, Db, Da, b[j]);
                 dprev = d1;
             }
         } else {
             // pairs (-1,0), (1,2), ..., (K-1,K): the lane's edge points pair
-            // with the neighbouring lanes' edge points
-            const T dm2 = dif(sl, el, sl2, el2);                      // d_{-2}
-            const T dm1 = dif(s[0], e[0], sl, el);                    // d_{-1}
-            const T d0 = dif(s[1], e[1], s[0], e[0]);                 // d_0
-            const T dK1 = dif(sr, er, s[K - 1], e[K - 1]);            // d_{K-1}
-            const T dK = dif(sr2, er2, sr, er);                       // d_K
-            const T dK2 = dif(s[K - 1], e[K - 1], s[K - 2], e[K - 2]);  // d_{K-2}
-            upd(0, d0 - dm1, dm1 - dm2, bl);
-            T dprev = d0;
+            // with the neighbouring lanes' edge points, so u_{-2} and u_{K+1}
+            // are needed too
+            const T sl2 = from_left(xl2, s[K - 2]), sr2 = from_right(xr2, s[1]);
+            T el2 = T(0), er2 = T(0);
+            if constexpr (COMP) { el2 = from_left(yl2, e[K - 2]); er2 = from_right(yr2, e[1]); }
+            const auto dm2 = dif(sl, el, sl2, el2);                   // d_{-2}
+            const auto dm1 = dif(s[0], e[0], sl, el);                 // d_{-1}
+            const auto d0 = dif(s[1], e[1], s[0], e[0]);              // d_0
+            const auto dK1 = dif(sr, er, s[K - 1], e[K - 1]);         // d_{K-1}
+            const auto dK = dif(sr2, er2, sr, er);                    // d_K
+            const auto dK2 = dif(s[K - 1], e[K - 1], s[K - 2], e[K - 2]);  // d_{K-2}
+            upd(0, sd(dm1, d0), sd(dm2, dm1), bl);
+            auto dprev = d0;
 #pragma unroll
             for (int q = 1; q < K / 2; ++q) {
                 const int j = 2 * q - 1;
-                const T da = dif(s[j + 1], e[j + 1], s[j], e[j]);    // d_j
-                const T db = dif(s[j + 2], e[j + 2], s[j + 1], e[j + 1]);  // d_{j+1}
-                const T Da = da - dprev, Db = db - da;
+                const auto da = dif(s[j + 1], e[j + 1], s[j], e[j]); // d_j
+                const auto db = dif(s[j + 2], e[j + 2], s[j + 1], e[j + 1]);  // d_{j+1}
+                const T Da = sd(dprev, da), Db = sd(da, db);
                 upd(j, Da, Db, b[j + 1]);
                 upd(j + 1, Db, Da, b[j]);
                 dprev = db;
             }
-            upd(K - 1, dK1 - dK2, dK - dK1, br);
+            upd(K - 1, sd(dK2, dK1), sd(dK1, dK), br);
         }
-
     }
 
     if (own_L && tid == 0) a.flux[0] = accL;
@@ -470,9 +527,9 @@ bool tile_config_supported(int prec, int k, int nw)
     if (nw != 1 && nw != 4)
         return false;
     switch (prec) {
-    case kFP64: return k == 8 || k == 16;
-    case kFP32: return k == 16 || k == 32;
-    case kFP32C: return k == 8 || k == 16;
+    case kFP64: return k == 2 || k == 4 || k == 8 || k == 16;
+    case kFP32: return k == 4 || k == 8 || k == 16 || k == 32;
+    case kFP32C: return k == 4 || k == 8 || k == 16;
     default: return false;
     }
 }
@@ -482,14 +539,19 @@ hipError_t launch_tiles(int prec, int k, int nw, bool src, const TileArgs &a,
 {
     switch (prec) {
     case kFP64:
+        if (k == 2) return launch_nw<double, 2, false>(nw, src, a, stream);
+        if (k == 4) return launch_nw<double, 4, false>(nw, src, a, stream);
         if (k == 8) return launch_nw<double, 8, false>(nw, src, a, stream);
         if (k == 16) return launch_nw<double, 16, false>(nw, src, a, stream);
         break;
     case kFP32:
+        if (k == 4) return launch_nw<float, 4, false>(nw, src, a, stream);
+        if (k == 8) return launch_nw<float, 8, false>(nw, src, a, stream);
         if (k == 16) return launch_nw<float, 16, false>(nw, src, a, stream);
         if (k == 32) return launch_nw<float, 32, false>(nw, src, a, stream);
         break;
     case kFP32C:
+        if (k == 4) return launch_nw<float, 4, true>(nw, src, a, stream);
         if (k == 8) return launch_nw<float, 8, true>(nw, src, a, stream);
         if (k == 16) return launch_nw<float, 16, true>(nw, src, a, stream);
         break;

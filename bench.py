@@ -32,10 +32,42 @@ N_DEFAULT = 1 << 24
 R = 2.0
 LEVELS = 10000
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector, published
-FP32_VECTOR_TFLOPS = 157.3
+# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s
+# (the published 78.6 TFLOP/s FP64 / 157.3 TFLOP/s packed-FP32 vector peaks
+# count every op as a fused multiply-add, 2 flops, and FP32 as packed pairs).
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# per update: algorithmic flops (fma = 2) and the fewest VALU instructions the
+# form can be written in -- FP64: 2 subtractions + 2 fma; FP32: 2 sub + mul +
+# fma + add (increment first); pair: 5 for D, mul + fma, 4 for the Kahan add
 FLOPS_PER_UPDATE = {"fp64": 6, "fp32": 6, "fp32c": 12}
+VALU_PER_UPDATE = {"fp64": 4, "fp32": 5, "fp32c": 11}
 BYTES_PER_POINT = {"fp64": 8, "fp32": 4, "fp32c": 8}
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "tile_sweep_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1310_3422_amd", "csrc", f)
+                  for f in ("ge_sweep.hip", "ge_level.h", "ge_kernels.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(key):
+    """HBM bytes per launch of the tile sweep from the committed counter
+    profile, if it was taken on the current kernel source; else None."""
+    try:
+        text = open(PROFILE_TRAFFIC).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch", {}).get(key)
 
 
 def launches_per_call(cfg, n_window_fits, nsteps):
@@ -87,12 +119,14 @@ def cpu_baseline(u0, target_s):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c", "fp32"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -108,6 +142,12 @@ def main():
 
     n = N_DEFAULT
     prec = args.precision
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     print(f"[bench] generating rod N={n} ...", file=sys.stderr, flush=True)
     u0 = inputs.sine_rod(n, seed=2)
     stream = torch.cuda.Stream()   # default priority
@@ -139,12 +179,16 @@ def main():
     kernel_s = gpu_s / nl
     upd_per_launch = n * LEVELS / (nl / args.steps)
     flops = FLOPS_PER_UPDATE[prec] * upd_per_launch
-    peak_tf = FP64_VECTOR_TFLOPS if prec == "fp64" else FP32_VECTOR_TFLOPS
+    peak_tf = VALU_LANE_OPS * FLOPS_PER_UPDATE[prec] / VALU_PER_UPDATE[prec] / 1e12
     achieved_tf = flops / kernel_s / 1e12
     hbm_bytes = 2 * BYTES_PER_POINT[prec] * n      # one read + one write per launch
+    tkey = f"{prec}_n{n}_k{cfg['tile']}_w{cfg['waves']}_d{cfg['depth']}"
     roofline = {
-        "bound": "alu", "achieved": round(achieved_tf, 3), "peak": peak_tf,
-        "unit": "TFLOP/s", "frac": round(achieved_tf / peak_tf, 4), "traffic": None,
+        "bound": "alu", "achieved": round(achieved_tf, 3), "peak": round(peak_tf, 2),
+        "unit": "TFLOP/s", "frac": round(achieved_tf / peak_tf, 4),
+        "traffic": recorded_traffic(tkey),
+        "peak_basis": f"VALU issue {VALU_LANE_OPS:.3g} lane-ops/s x {FLOPS_PER_UPDATE[prec]} "
+                      f"flops / {VALU_PER_UPDATE[prec]} VALU ops per update",
         "kernel": f"tile_kernel<{'double' if prec == 'fp64' else 'float'},{cfg['tile']},"
                   f"{cfg['waves']},{'comp' if prec == 'fp32c' else 'plain'}>",
         "depth": cfg["depth"], "launches": nl, "avg_launch_us": round(kernel_s * 1e6, 2),

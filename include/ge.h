@@ -145,12 +145,20 @@ ge_status ge_comp_to_fp64(const float *pair, double *x, int64_t n, void *stream)
 ge_status ge_comp_from_fp64(const double *x, float *pair, int64_t n, void *stream);
 
 /* ------------------------------------------------------------------------
- * Batch of independent rods (same scheme, each rod with its own n, r and
- * constant walls) advanced by the same number of levels in one persistent
- * launch.  Rod i occupies u[offsets[i] .. offsets[i] + n[i]) (in elements;
- * GE_FP32_COMP stores the s block of every rod first, then the e block at
- * the same offsets shifted by offsets[nrods]).  offsets[i] must be a
- * multiple of 4 and offsets[i+1] >= offsets[i] + n[i].
+ * Batch of independent rods: the same scheme (Section 2) for every rod, each
+ * rod with its own n, r and constant wall values, all advanced by the same
+ * levels in one persistent launch that a hipGraph captures.
+ *
+ * Layout of the packed state u: rod i occupies elements
+ * offsets[i] .. offsets[i] + n[i] - 1 (double for GE_FP64, float for the two
+ * FP32 forms).  For GE_FP32_COMP the e parts follow in a second block at
+ * element offset ge_comp_offset(offsets[nrods]); ge_batch_state_elems() gives
+ * the buffer length in elements.  Every offsets[i] must be a multiple of 4 and
+ * offsets[i+1] >= offsets[i] + n[i].
+ *
+ * Each rod is held in registers of one workgroup for all levels, which caps
+ * n at 65536 (GE_FP32) or 32768 (GE_FP64, GE_FP32_COMP); longer rods go
+ * through ge_step_n.
  * ---------------------------------------------------------------------- */
 typedef struct ge_batch_s *ge_batch_t;
 
@@ -161,25 +169,45 @@ typedef struct {
     const double *r;         /* host, nrods: mesh ratio of each rod           */
     const double *g_left;    /* host, nrods: constant left wall values        */
     const double *g_right;   /* host, nrods: constant right wall values       */
-    int32_t precision;       /* GE_FP32 or GE_FP64 (GE_FP32_COMP: see above)  */
-    int32_t tune;            /* 0 = use the tuned/cached choice, 1 = re-tune  */
+    int32_t precision;       /* ge_precision                                  */
+    int32_t tune;            /* 1: measure the per-level cost of each         */
+                             /* points-per-lane choice on this device now and */
+                             /* store it (file $GE_TUNE_CACHE, default        */
+                             /* ~/.cache/libge/batch_tune.txt); 0: use the    */
+                             /* stored measurement, or built-in defaults      */
 } ge_batch_desc;
 
-/* Create a batch plan.  Copies the rod table to device memory the plan
- * owns (the only device allocation the library makes; freed by
- * ge_batch_destroy).  Errors: GE_ERR_INVALID, GE_ERR_NONFINITE,
- * GE_ERR_UNSUPPORTED (a rod too long for the on-chip kernel), GE_ERR_NOMEM,
- * GE_ERR_HIP. */
+/* Create a batch plan: choose points per lane for every rod, bundle rods
+ * into workgroup tasks, order them largest first, and copy the rod and task
+ * tables to device memory owned by the plan (freed by ge_batch_destroy).
+ * With tune = 1 this runs timing kernels on the current device.  Every
+ * choice gives bit-identical results.  Errors: GE_ERR_INVALID,
+ * GE_ERR_NONFINITE, GE_ERR_UNSUPPORTED (a rod above the on-chip limit),
+ * GE_ERR_NOMEM, GE_ERR_HIP. */
 ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *desc);
+
+/* Release a batch plan and its graph (NULL is ignored). */
 void ge_batch_destroy(ge_batch_t batch);
 
-/* Bytes of device workspace ge_solve_batch needs. */
+/* Elements of the packed state buffer (see the layout above); -1 for NULL. */
+int64_t ge_batch_state_elems(ge_batch_t batch);
+
+/* Bytes of device workspace ge_solve_batch needs (the task queue head). */
 size_t ge_batch_workspace_bytes(ge_batch_t batch);
 
-/* Advance every rod from level step0 by nsteps levels, in place in `u`
- * (device, packed as described above), in one persistent launch that pulls
- * rods from a queue, largest first.  workspace: device,
- * ge_batch_workspace_bytes() bytes, 256-byte aligned. */
+/* The plan's shape: number of tasks, resident workgroups, the planner's
+ * estimate of the time of one level in microseconds, and (if rod_k is not
+ * NULL, host, nrods entries) the points per lane chosen for each rod. */
+ge_status ge_batch_info(ge_batch_t batch, int32_t *ntasks, int32_t *grid,
+                        double *est_us_per_level, int32_t *rod_k);
+
+/* Advance every rod from level step0 by nsteps levels, in place in u
+ * (device, packed as above, 16-byte aligned).  workspace: device,
+ * ge_batch_workspace_bytes() bytes, 256-byte aligned; it must not be used
+ * by another run at the same time.  The first call for a given (u,
+ * workspace, parity of step0, nsteps) captures the queue reset and the
+ * persistent launch in a hipGraph; later calls with the same key replay it
+ * on `stream`.  Errors: GE_ERR_INVALID, GE_ERR_HIP. */
 ge_status ge_solve_batch(ge_batch_t batch, void *u, void *workspace,
                          int64_t step0, int64_t nsteps, void *stream);
 

@@ -10,27 +10,56 @@
 #include <string>
 
 #include "ge.h"
+#include "ge_internal.h"
 #include "ge_kernels.h"
 
 namespace ge {
 
 int64_t comp_offset(int64_t n) { return (n + 63) / 64 * 64; }
 
+namespace {
+thread_local std::string g_last_error;
+}
+
+ge_status vset_error(ge_status st, const char *fmt, va_list ap)
+{
+    char buf[512];
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    g_last_error = buf;
+    return st;
+}
+
+ge_status set_error(ge_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vset_error(st, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+const char *last_error_str() { return g_last_error.c_str(); }
+
+SchemeCoef scheme_coef(double r)
+{
+    SchemeCoef c;
+    c.c1 = (r + r * r) / (1.0 + 2.0 * r);
+    c.c2 = (r * r) / (1.0 + 2.0 * r);
+    c.cs = r / (1.0 + r);
+    return c;
+}
+
 }  // namespace ge
 
 namespace {
 
-thread_local std::string g_last_error;
-
 ge_status fail(ge_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 ge_status fail(ge_status st, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    ge::vset_error(st, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
     return st;
 }
 
@@ -74,7 +103,7 @@ extern "C" {
 
 const char *ge_version(void) { return "0.1.0"; }
 
-const char *ge_last_error(void) { return g_last_error.c_str(); }
+const char *ge_last_error(void) { return ge::last_error_str(); }
 
 const char *ge_status_str(int status)
 {
@@ -118,9 +147,12 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
 
     const int prec = d->precision;
     int tile = d->tile, waves = d->waves, depth = d->depth;
-    if (tile == 0) tile = (prec == ge::kFP32) ? 32 : 16;
-    if (waves == 0) waves = 4;
-    if (depth == 0) depth = 32;
+    // Defaults measured on MI355X for long rods (16 points per lane, one
+    // wave per workgroup, 48 levels per launch was the fastest choice for all
+    // three precisions on n = 2^24).
+    if (tile == 0) tile = 16;
+    if (waves == 0) waves = 1;
+    if (depth == 0) depth = 48;
     if (depth < 1)
         return fail(GE_ERR_INVALID, "ge_plan: depth = %d, need depth >= 1", depth);
     if (!ge::tile_config_supported(prec, tile, waves))
@@ -164,9 +196,10 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
     const double r = p->r;
     p->h = 1.0 / (double)(p->n + 1);
     p->tau = r * p->h * p->h;
-    p->c1 = (r + r * r) / (1.0 + 2.0 * r);
-    p->c2 = (r * r) / (1.0 + 2.0 * r);
-    p->cs = r / (1.0 + r);
+    const ge::SchemeCoef sc = ge::scheme_coef(r);
+    p->c1 = sc.c1;
+    p->c2 = sc.c2;
+    p->cs = sc.cs;
     p->e1 = p->tau * (1.0 + r) / (1.0 + 2.0 * r);
     p->e2 = p->tau * r / (1.0 + 2.0 * r);
     p->es = p->tau / (1.0 + r);
@@ -201,8 +234,8 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
     if (!aligned16(u))
         return fail(GE_ERR_INVALID, "ge_step_n: u must be 16-byte aligned");
     if ((plan->src_b != nullptr) != (src_a_t != nullptr))
-        return fail(GE_ERR_INVALID, plan->src_b ? "ge_step_n: the plan has a source, src_a_t is NULL"
-                                                : "ge_step_n: src_a_t given but the plan has no source");
+        return fail(GE_ERR_INVALID, "%s", plan->src_b ? "ge_step_n: the plan has a source, src_a_t is NULL"
+                                                      : "ge_step_n: src_a_t given but the plan has no source");
     const size_t bytes = (size_t)state_elems(plan->prec, plan->n) * elem_bytes(plan->prec);
     if (!plan->single) {
         if (!workspace)
@@ -295,37 +328,6 @@ ge_status ge_comp_from_fp64(const double *x, float *pair, int64_t n, void *strea
         return fail(GE_ERR_INVALID, "ge_comp_from_fp64: bad arguments");
     hipError_t e = ge::launch_comp_from_fp64(x, pair, n, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? GE_OK : hip_fail(e, "ge_comp_from_fp64");
-}
-
-}  // extern "C"
-
-// ---- batch of rods (not built yet) ---------------------------------------
-struct ge_batch_s {
-    int64_t nrods;
-};
-
-extern "C" {
-
-ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *desc)
-{
-    if (out) *out = nullptr;
-    (void)desc;
-    return fail(GE_ERR_UNSUPPORTED, "ge_batch_plan: not available in this build");
-}
-
-void ge_batch_destroy(ge_batch_t batch) { delete batch; }
-
-size_t ge_batch_workspace_bytes(ge_batch_t batch)
-{
-    (void)batch;
-    return 0;
-}
-
-ge_status ge_solve_batch(ge_batch_t batch, void *u, void *workspace, int64_t step0,
-                         int64_t nsteps, void *stream)
-{
-    (void)batch; (void)u; (void)workspace; (void)step0; (void)nsteps; (void)stream;
-    return fail(GE_ERR_UNSUPPORTED, "ge_solve_batch: not available in this build");
 }
 
 }  // extern "C"

@@ -1,0 +1,42 @@
+// Internal interface of the persistent batch sweep (ge_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ge {
+
+constexpr int kBatchWaves = 16;   // waves per workgroup of the batch kernel
+
+// One rod, as the device sees it.
+struct BatchRod {
+    int64_t off;              // element offset of the rod's first point in u
+    int64_t n;                // interior points
+    double c1, c2, cs;        // (r+r^2)/(1+2r), r^2/(1+2r), r/(1+r)
+    double gl, gr;            // constant wall values
+};
+
+// One unit of work for a workgroup: rods sharing points-per-lane k, each
+// owning a contiguous range of the workgroup's waves (-1: wave idle).
+struct BatchTask {
+    int32_t k;
+    int32_t pad;
+    int32_t wave_rod[kBatchWaves];   // rod index per wave
+    int32_t wave_idx[kBatchWaves];   // wave index within its rod
+};
+
+struct BatchArgs {
+    void *u;                  // packed state (s block; e block at estride)
+    const BatchRod *rods;
+    const BatchTask *tasks;   // largest first
+    int *counter;             // queue head, reset by a kernel before each run
+    int64_t estride;          // FP32C: element offset of the e block
+    int64_t step0;
+    int32_t nsteps;
+    int32_t ntasks;
+};
+
+hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream);
+int batch_max_k(int prec);
+
+}  // namespace ge

@@ -1,0 +1,207 @@
+// Persistent batch sweep: thousands of independent rods (each with its own n,
+// r and constant walls) advanced by the same number of levels in one launch.
+//
+// Each workgroup of 16 waves stays resident and pulls tasks from a queue
+// (largest first).  A task is a bundle of rods that share a points-per-lane
+// choice K; each rod owns a contiguous range of the workgroup's waves and is
+// held entirely in registers for all levels, so a rod is read and written
+// once per launch.  Per level the waves of a rod exchange their edge values
+// through LDS (one workgroup barrier per level) and the per-point update is
+// the shared ge_level (ge_level.h), so every rod evolves bit for bit as it
+// does through ge_step_n.  The queue counter is reset by a kernel node, and
+// the reset and the sweep are captured in a hipGraph that later calls
+// replay.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ge.h"
+#include "ge_batch.h"
+#include "ge_kernels.h"
+#include "ge_level.h"
+
+namespace ge {
+namespace {
+
+using namespace dev;
+
+constexpr int kWaves = kBatchWaves;          // waves per workgroup
+constexpr int kThreads = kWaves * kWave;
+
+template <typename T, int K, bool COMP, bool WALL>
+__device__ __forceinline__ void rod_levels(const BatchArgs &a, const BatchRod &rd, int wr,
+                                           T (&s)[K], T (&e)[K], T (*xs)[kWaves][4],
+                                           T (*xe)[kWaves][4])
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    // the wave index is uniform across the wave: let the compiler keep
+    // everything derived from it in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int64_t n = rd.n;
+    const int64_t w0 = (int64_t)wr * kWave * K;       // rod index of this wave's first point
+    const int64_t q = n - w0;                         // wave position of the right wall node
+    const bool left_wall = (wr == 0);
+    const bool ghost_in = (q >= 0) && (q < (int64_t)kWave * K);
+    const bool ghost_edge = (q == (int64_t)kWave * K);
+    const int kR = ghost_in ? (int)(q % K) : 0;
+    const int lR = ghost_in ? (int)(q / K) : -1;
+    const int64_t qS = q - 1;
+    const bool has_S = (qS >= 0) && (qS < (int64_t)kWave * K);
+    const int kS = has_S ? (int)(qS % K) : 0;
+    const int lS = has_S ? (int)(qS / K) : -1;
+    T gl_hi, gl_lo, gr_hi, gr_lo;
+    split_wall<T, COMP>(rd.gl, gl_hi, gl_lo);
+    split_wall<T, COMP>(rd.gr, gr_hi, gr_lo);
+    const Coef<T> cf{(T)rd.c1, (T)rd.c2, (T)rd.cs, T(0), T(0), T(0)};
+    const T b0[K] = {};
+    FluxTap ft{false, 0.0, 0.0, 1.0, 0.0};
+
+    for_levels(a.step0, a.nsteps, [&](auto par, int lev) {
+        constexpr int p = decltype(par)::value;
+        if (WALL && ghost_in) {
+            put_at<T, K>(s, kR, lane == lR, gr_hi);
+            if constexpr (COMP) put_at<T, K>(e, kR, lane == lR, gr_lo);
+        }
+        const int pb = lev & 1;
+        if (lane == 0) { xs[pb][w][0] = s[0]; xs[pb][w][1] = s[1]; }
+        if (lane == kWave - 1) { xs[pb][w][2] = s[K - 2]; xs[pb][w][3] = s[K - 1]; }
+        if constexpr (COMP) {
+            if (lane == 0) { xe[pb][w][0] = e[0]; xe[pb][w][1] = e[1]; }
+            if (lane == kWave - 1) { xe[pb][w][2] = e[K - 2]; xe[pb][w][3] = e[K - 1]; }
+        }
+        __syncthreads();
+        const int wl = w > 0 ? w - 1 : 0, wrr = w < kWaves - 1 ? w + 1 : kWaves - 1;
+        T xl = xs[pb][wl][3], xr = xs[pb][wrr][0], xl2 = xs[pb][wl][2], xr2 = xs[pb][wrr][1];
+        T yl = T(0), yr = T(0), yl2 = T(0), yr2 = T(0);
+        if constexpr (COMP) {
+            yl = xe[pb][wl][3]; yr = xe[pb][wrr][0]; yl2 = xe[pb][wl][2]; yr2 = xe[pb][wrr][1];
+        }
+        WallLevel<T> wlv{false, T(0)};
+        bool singR = false;
+        if constexpr (WALL) {
+            if (left_wall) { xl = gl_hi; if constexpr (COMP) yl = gl_lo; }
+            if (ghost_edge) { xr = gr_hi; if constexpr (COMP) yr = gr_lo; }
+            wlv.isL = left_wall && (p == 1) && (lane == 0);
+            singR = has_S && (((n - 1 + p) & 1) == 0);
+        }
+        Lone<T> lone{T(0), T(0)};
+        if (WALL && singR)
+            lone = right_lone<T, K, COMP, false>(s, e, b0, kS, xl, yl, gr_hi, gr_lo, T(0), cf,
+                                                 T(0));
+        ge_level<T, K, COMP, false, WALL, p>(s, e, b0, T(0), T(0), xl, xl2, xr, xr2, yl, yl2,
+                                             yr, yr2, cf, T(0), wlv, ft);
+        if (WALL && singR) {
+            put_at<T, K>(s, kS, lane == lS, lone.s);
+            if constexpr (COMP) put_at<T, K>(e, kS, lane == lS, lone.e);
+        }
+    });
+}
+
+// Every wave of the workgroup executes the same number of barriers: waves
+// without a rod in this task run the level loop on dummy data.
+template <typename T, int K, bool COMP>
+__device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk)
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    // the wave index is uniform across the wave: let the compiler keep
+    // everything derived from it in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    __shared__ T xs[2][kWaves][4];
+    __shared__ T xe[2][kWaves][4];
+    const int rod = tk.wave_rod[w];
+    const int wr = tk.wave_idx[w];
+    T s[K], e[K];
+    BatchRod rd{};
+    T *us = nullptr, *ue = nullptr;
+    int64_t g0 = 0;
+    if (rod >= 0) {
+        rd = a.rods[rod];
+        us = static_cast<T *>(a.u) + rd.off;
+        ue = static_cast<T *>(a.u) + a.estride + rd.off;
+        g0 = ((int64_t)wr * kWave + lane) * K;
+        load_lane_guarded<T, K>(us + g0, g0, rd.n, s);
+        if constexpr (COMP) load_lane_guarded<T, K>(ue + g0, g0, rd.n, e);
+    } else {
+        rd.n = (int64_t)kWave * K;
+        rd.c1 = rd.c2 = rd.cs = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) s[j] = T(0);
+    }
+    if constexpr (!COMP) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) e[j] = T(0);
+    }
+    const int64_t w0 = (int64_t)wr * kWave * K;
+    const bool wall = (rod >= 0) && (wr == 0 || rd.n - w0 <= (int64_t)kWave * K);
+    if (wall)
+        rod_levels<T, K, COMP, true>(a, rd, wr, s, e, xs, xe);
+    else
+        rod_levels<T, K, COMP, false>(a, rd, wr, s, e, xs, xe);
+    if (rod >= 0) {
+        store_lane_upto<T, K>(us + g0, g0, rd.n, s);
+        if constexpr (COMP) store_lane_upto<T, K>(ue + g0, g0, rd.n, e);
+    }
+    __syncthreads();   // LDS slots are reused by the next task
+}
+
+template <typename T, bool COMP>
+__global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
+{
+    __shared__ int task_s;
+    for (;;) {
+        if (threadIdx.x == 0)
+            task_s = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int task = task_s;
+        __syncthreads();
+        if (task >= a.ntasks)
+            break;
+        const BatchTask &tk = a.tasks[task];
+        switch (tk.k) {
+        case 4: run_task<T, 4, COMP>(a, tk); break;
+        case 8: run_task<T, 8, COMP>(a, tk); break;
+        case 16: run_task<T, 16, COMP>(a, tk); break;
+        case 32: run_task<T, 32, COMP>(a, tk); break;
+        case 64:
+            if constexpr (sizeof(T) == 4 && !COMP) run_task<T, 64, COMP>(a, tk);
+            break;
+        default: break;
+        }
+    }
+}
+
+__global__ void reset_counter_kernel(int *counter) { *counter = 0; }
+
+}  // namespace
+
+hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream)
+{
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, a.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (prec) {
+    case kFP64:
+        hipLaunchKernelGGL((batch_kernel<double, false>), dim3(grid), dim3(kThreads), 0, stream, a);
+        break;
+    case kFP32:
+        hipLaunchKernelGGL((batch_kernel<float, false>), dim3(grid), dim3(kThreads), 0, stream, a);
+        break;
+    case kFP32C:
+        hipLaunchKernelGGL((batch_kernel<float, true>), dim3(grid), dim3(kThreads), 0, stream, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int batch_max_k(int prec) { return prec == kFP32 ? 64 : 32; }
+
+}  // namespace ge

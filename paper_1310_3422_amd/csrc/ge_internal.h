@@ -1,0 +1,29 @@
+// Helpers shared by the host-side C ABI sources.
+#pragma once
+
+#include <stdarg.h>
+#include <stdint.h>
+
+#include "ge.h"
+
+namespace ge {
+
+// Record a printf-style message as the calling thread's last error and
+// return `st`.
+ge_status set_error(ge_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+ge_status vset_error(ge_status st, const char *fmt, va_list ap);
+
+// Coefficients of the scheme for mesh ratio r, evaluated on the host in FP64
+// by the same expressions for every entry point (single rod and batch), so
+// both paths feed the kernels identical values.
+struct SchemeCoef {
+    double c1, c2, cs;   // (r+r^2)/(1+2r), r^2/(1+2r), r/(1+r)
+};
+SchemeCoef scheme_coef(double r);
+
+int64_t comp_offset(int64_t n);
+
+// Message recorded by the last set_error on the calling thread.
+const char *last_error_str();
+
+}  // namespace ge

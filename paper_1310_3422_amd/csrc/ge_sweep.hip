@@ -1,193 +1,30 @@
-// Tiled, temporally blocked GE sweep for gfx950.
+// Tiled, temporally blocked GE sweep of one rod for gfx950.
 //
-// Scheme (Section 2, two-point groups): at level m with p = m mod 2 the
-// points are coupled as (0,1),(2,3),... (0-based) when p = 0 and
-// (1,2),(3,4),... when p = 1.  A coupled pair solved by the confluence
-// formulas Eq. (3)/(4) is written here in the equivalent second-difference
-// form: with D_i = u_{i-1} - 2u_i + u_{i+1},
-//     u_i' = u_i + c1 D_i + c2 D_q,   c1 = (r+r^2)/(1+2r), c2 = r^2/(1+2r),
-// where q is i's partner.  A point alone beside a wall (point 0 when p = 1,
-// point n-1 when n-1+p is even) takes scheme A, Eq. (1), or scheme B,
-// Eq. (2), in the same form: u_i' = u_i + cs (D_i + g(t_{m+1}) - g(t_m)),
-// cs = r/(1+r), where D_i used the wall value at t_m.  A source f = a(t) b(x)
-// adds a(t_m + tau/2) (e1 b_i + e2 b_q) to a pair member and
-// a(t_m + tau/2) es b_i to a lone point.
-//
-// D_i is formed from first differences d_i = u_{i+1} - u_i as
-// D_i = d_i - d_{i-1}; for smooth data the differences are exact, so the
-// increment carries a relative (not absolute) rounding error.  FP64 then
-// applies u' = fma(c2, D_q, fma(c1, D_i, u)); FP32 forms the increment
-// first and rounds u once per level.  The compensated FP32 pair (s, e),
-// value s + e, takes D from the s and e second differences summed at the
-// end, and adds the increment with Kahan's compensated sum.
-//
-// Mapping: one workgroup of NW waves owns a window of W = NW*64*K points;
-// lane l of wave w holds points (64w + l)K .. (64w + l)K + K-1 of the window
-// in registers.  Neighbour values cross lanes by DPP wave shifts and waves by
-// LDS (one barrier per level).  A value at level m+1 depends on level-m
-// values at most two places away, and after the first level the invalid
-// region entering from an open window edge grows by one point per level, so
-// a halo of H >= nlev + 1 points each side leaves the core exact; halos are
-// recomputed by the neighbouring tiles instead of being exchanged.
-//
-// Determinism: every point of every tile, halo or core, wall tile or not, is
-// advanced by the same expression sequence with explicit fma() and no
-// contraction (-ffp-contract=off), so results do not depend on the tiling,
-// the levels per launch or the grid.
+// One workgroup of NW waves owns a window of W = NW*64*K points; lane l of
+// wave w holds points (64w + l)K .. (64w + l)K + K-1 of the window in
+// registers and the window advances nlev levels there (ge_level.h).  Edge
+// values cross waves through LDS, one barrier per level.  A value at level
+// m+1 depends on level-m values at most two places away, and after the first
+// level the invalid region entering from an open window edge grows by one
+// point per level, so a halo of H >= nlev + 1 points each side leaves the
+// core exact; halos are recomputed by the neighbouring tiles instead of being
+// exchanged, and no data crosses workgroups inside a launch.
 #include "ge_kernels.h"
+#include "ge_level.h"
 
 namespace ge {
 namespace {
 
-constexpr int kWave = 64;
-
-// ---- cross-lane moves ------------------------------------------------------
-// DPP wave shifts by one lane; the lane with no source (lane 0 for a shift
-// right, lane 63 for a shift left) receives `fill`.
-__device__ __forceinline__ int shr1_i(int fill, int v)
-{
-    return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xF, 0xF, false);  // wave_shr:1
-}
-__device__ __forceinline__ int shl1_i(int fill, int v)
-{
-    return __builtin_amdgcn_update_dpp(fill, v, 0x130, 0xF, 0xF, false);  // wave_shl:1
-}
-// value held by lane l-1 (lane 0: fill)
-__device__ __forceinline__ float from_left(float fill, float v)
-{
-    return __int_as_float(shr1_i(__float_as_int(fill), __float_as_int(v)));
-}
-// value held by lane l+1 (lane 63: fill)
-__device__ __forceinline__ float from_right(float fill, float v)
-{
-    return __int_as_float(shl1_i(__float_as_int(fill), __float_as_int(v)));
-}
-__device__ __forceinline__ double from_left(double fill, double v)
-{
-    const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
-    const int lo = shr1_i((int)(f & 0xffffffffll), (int)(b & 0xffffffffll));
-    const int hi = shr1_i((int)(f >> 32), (int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double from_right(double fill, double v)
-{
-    const long long b = __double_as_longlong(v), f = __double_as_longlong(fill);
-    const int lo = shl1_i((int)(f & 0xffffffffll), (int)(b & 0xffffffffll));
-    const int hi = shl1_i((int)(f >> 32), (int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// ---- 16-byte vector access to a lane's K contiguous values ----------------
-template <typename T> struct V16;
-template <> struct V16<float> { using type = float4; static constexpr int E = 4; };
-template <> struct V16<double> { using type = double2; static constexpr int E = 2; };
-
-template <typename T, int K>
-__device__ __forceinline__ void load_lane(const T *__restrict__ p, T (&v)[K])
-{
-    using V = typename V16<T>::type;
-    constexpr int E = V16<T>::E;
-    static_assert(K % E == 0, "K must fill whole 16-byte chunks");
-    const V *q = reinterpret_cast<const V *>(p);
-#pragma unroll
-    for (int c = 0; c < K / E; ++c) {
-        const V x = q[c];
-        if constexpr (E == 4) {
-            v[4 * c] = x.x; v[4 * c + 1] = x.y; v[4 * c + 2] = x.z; v[4 * c + 3] = x.w;
-        } else {
-            v[2 * c] = x.x; v[2 * c + 1] = x.y;
-        }
-    }
-}
-
-template <typename T, int K>
-__device__ __forceinline__ void load_lane_guarded(const T *__restrict__ p, int64_t g0,
-                                                  int64_t n, T (&v)[K])
-{
-    using V = typename V16<T>::type;
-    constexpr int E = V16<T>::E;
-    const V *q = reinterpret_cast<const V *>(p);
-#pragma unroll
-    for (int c = 0; c < K / E; ++c) {
-        if (g0 + (c + 1) * E <= n) {
-            const V x = q[c];
-            if constexpr (E == 4) {
-                v[4 * c] = x.x; v[4 * c + 1] = x.y; v[4 * c + 2] = x.z; v[4 * c + 3] = x.w;
-            } else {
-                v[2 * c] = x.x; v[2 * c + 1] = x.y;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < E; ++i)
-                v[c * E + i] = (g0 + c * E + i < n) ? p[c * E + i] : T(0);
-        }
-    }
-}
-
-// Store the values whose global index lies in [lo, hi).  lo and hi are
-// multiples of the chunk width on the fast path.
-template <typename T, int K>
-__device__ __forceinline__ void store_lane_chunks(T *__restrict__ p, int64_t g0, int64_t lo,
-                                                  int64_t hi, const T (&v)[K])
-{
-    using V = typename V16<T>::type;
-    constexpr int E = V16<T>::E;
-    V *q = reinterpret_cast<V *>(p);
-#pragma unroll
-    for (int c = 0; c < K / E; ++c) {
-        const int64_t g = g0 + c * E;
-        if (g >= lo && g < hi) {
-            V x;
-            if constexpr (E == 4) {
-                x.x = v[4 * c]; x.y = v[4 * c + 1]; x.z = v[4 * c + 2]; x.w = v[4 * c + 3];
-            } else {
-                x.x = v[2 * c]; x.y = v[2 * c + 1];
-            }
-            q[c] = x;
-        }
-    }
-}
-
-template <typename T, int K>
-__device__ __forceinline__ void store_lane_guarded(T *__restrict__ p, int64_t g0, int64_t lo,
-                                                   int64_t hi, const T (&v)[K])
-{
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-        if (g0 + j >= lo && g0 + j < hi)
-            p[j] = v[j];
-}
-
-// v[k] = x in the lanes where `pred` holds; k is uniform across the wave.
-template <typename T, int K>
-__device__ __forceinline__ void put_at(T (&v)[K], int k, bool pred, T x)
-{
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-        if (j == k)
-            v[j] = pred ? x : v[j];
-}
-
-// A first difference: one value, or the (s, e) parts of the pair kept apart.
-template <typename T, bool COMP> struct Dif { T s; };
-template <typename T> struct Dif<T, true> { T s, e; };
-
-// Wall value split for the state type: (hi, lo) with hi + lo ~ g.
-template <typename T, bool COMP>
-__device__ __forceinline__ void split_wall(double g, T &hi, T &lo)
-{
-    hi = (T)g;
-    lo = COMP ? (T)(g - (double)hi) : T(0);
-}
+using namespace dev;
 
 template <typename T, int K, int NW, bool COMP, bool SRC, bool WALL>
 __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t ws)
 {
     constexpr int W = NW * kWave * K;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    // the wave index is uniform across the wave: let the compiler keep
+    // everything derived from it in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int64_t n = a.n;
     const int64_t core_lo = t * a.core;
     const int64_t core_hi = min(core_lo + a.core, n);
@@ -250,11 +87,11 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
     if (own_L) accL = a.flux[0];
     if (own_R) accR = a.flux[1];
 
-    const T c1 = (T)a.c1, c2 = (T)a.c2, cs = (T)a.cs;
-    const T e1 = (T)a.e1, e2 = (T)a.e2, es = (T)a.es;
+    const Coef<T> cf{(T)a.c1, (T)a.c2, (T)a.cs, (T)a.e1, (T)a.e2, (T)a.es};
+    FluxTap ft{own_L && tid == 0, accL, a.tau, a.h, 0.0};
 
-    for (int lev = 0; lev < a.nlev; ++lev) {
-        const int p = (int)((a.level0 + lev) & 1);
+    for_levels(a.level0, a.nlev, [&](auto par, int lev) {
+        constexpr int p = decltype(par)::value;
         double glo = a.gl0, gln = a.gl0, gro = a.gr0, grn = a.gr0;
         if constexpr (WALL) {
             if (a.gl_t) { glo = a.gl_t[lev]; gln = a.gl_t[lev + 1]; }
@@ -289,8 +126,9 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
                 yl2 = xe[pb][wl][2]; yr2 = xe[pb][wr][1];
             }
         }
-        T dgl = T(0), dgr = T(0);
-        bool isL = false, isS = false;
+        WallLevel<T> wlv{false, T(0)};
+        T gr_hi = T(0), gr_lo = T(0), dgr = T(0);
+        bool singR = false;
         if constexpr (WALL) {
             if (left_wall && w == 0) {
                 T gh, glw;
@@ -304,144 +142,31 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
                 xr = gh;
                 if constexpr (COMP) yr = glw;
             }
-            dgl = (T)(gln - glo);
+            wlv.dgl = (T)(gln - glo);
+            wlv.isL = left_wall && (p == 1) && (tid == 0);
+            ft.gln = gln;
+            split_wall<T, COMP>(gro, gr_hi, gr_lo);
             dgr = (T)(grn - gro);
-            isL = left_wall && (p == 1) && (tid == 0);
-            isS = has_S && (((n - 1 + p) & 1) == 0) && (tid == lS);
+            singR = has_S && (((n - 1 + p) & 1) == 0);
         }
-        // u_{-1} and u_K: neighbour lanes' edge points
-        const T sl = from_left(xl, s[K - 1]), sr = from_right(xr, s[0]);
-        T el = T(0), er = T(0);
-        if constexpr (COMP) { el = from_left(yl, e[K - 1]); er = from_right(yr, e[0]); }
         const T an = SRC ? (T)a.src_a[lev] : T(0);
-
-        // First difference u_{j+1} - u_j of two points given as (s, e).  For
-        // the pair the s and e parts stay apart: for smooth data the s
-        // differences (and their differences) are exact, and summing the s
-        // and e second differences only at the end keeps D accurate to the
-        // precision of the pair.
-        auto dif = [&](T s1, T e1_, T s0, T e0) -> Dif<T, COMP> {
-            if constexpr (COMP) return Dif<T, COMP>{s1 - s0, e1_ - e0};
-            else return Dif<T, COMP>{s1 - s0};
-        };
-        // second difference D = db - da from consecutive first differences
-        auto sd = [&](Dif<T, COMP> da, Dif<T, COMP> db) -> T {
-            if constexpr (COMP) return (db.s - da.s) + (db.e - da.e);
-            else return db.s - da.s;
-        };
-        // advance point j from D_self and D_partner (bp: partner's profile)
-        auto upd = [&](int j, T Ds, T Dp, T bp) {
-            if constexpr (COMP) {
-                T inc = fmaT(c1, Ds, c2 * Dp);
-                if constexpr (SRC) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
-                if constexpr (WALL) {
-                    if (j == kS) {
-                        T alt = cs * (Ds + dgr);
-                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
-                        inc = isS ? alt : inc;
-                    }
-                    if (j == 0) {
-                        T alt = cs * (Ds + dgl);
-                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
-                        inc = isL ? alt : inc;
-                    }
-                }
-                // Kahan: the pair absorbs the increment, e keeps what s lost
-                const T y = inc + e[j];
-                const T tt = s[j] + y;
-                e[j] = y - (tt - s[j]);
-                s[j] = tt;
-            } else if constexpr (sizeof(T) == 8) {
-                // FP64: two fused steps, u + c1 D_self, then + c2 D_partner
-                T t = fmaT(c1, Ds, s[j]);
-                if constexpr (SRC) t = fmaT(an, fmaT(e1, b[j], e2 * bp), t);
-                T v = fmaT(c2, Dp, t);
-                if constexpr (WALL) {
-                    if (j == kS) {
-                        T alt = fmaT(cs, Ds + dgr, s[j]);
-                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
-                        v = isS ? alt : v;
-                    }
-                    if (j == 0) {
-                        T alt = fmaT(cs, Ds + dgl, s[j]);
-                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
-                        v = isL ? alt : v;
-                    }
-                }
-                s[j] = v;
-            } else {
-                // FP32: form the increment first, so u is rounded once per level
-                T inc = fmaT(c1, Ds, c2 * Dp);
-                if constexpr (SRC) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
-                if constexpr (WALL) {
-                    if (j == kS) {
-                        T alt = cs * (Ds + dgr);
-                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
-                        inc = isS ? alt : inc;
-                    }
-                    if (j == 0) {
-                        T alt = cs * (Ds + dgl);
-                        if constexpr (SRC) alt = fmaT(an, es * b[j], alt);
-                        inc = isL ? alt : inc;
-                    }
-                }
-                s[j] = s[j] + inc;
-            }
-            if constexpr (WALL) {
-                // wall first differences at the new level, accumulated in FP64
-                if (own_L && j == 0 && tid == 0) {
-                    const double v = (double)s[j] + (COMP ? (double)e[j] : 0.0);
-                    accL = accL + a.tau * (v - gln) / a.h;
-                }
-                if (own_R && j == kS && tid == lS) {
-                    const double v = (double)s[j] + (COMP ? (double)e[j] : 0.0);
-                    accR = accR + a.tau * (v - grn) / a.h;
-                }
-            }
-        };
-
-        if (p == 0) {
-            // pairs (2q, 2q+1) inside the lane
-            auto dprev = dif(s[0], e[0], sl, el);                    // d_{-1}
-#pragma unroll
-            for (int q = 0; q < K / 2; ++q) {
-                const int j = 2 * q;
-                const auto d0 = dif(s[j + 1], e[j + 1], s[j], e[j]); // d_j
-                const auto d1 = (j + 2 < K) ? dif(s[j + 2], e[j + 2], s[j + 1], e[j + 1])
-                                            : dif(sr, er, s[j + 1], e[j + 1]);
-                const T Da = sd(dprev, d0), Db = sd(d0, d1);
-                upd(j, Da, Db, b[j + 1]);
-                upd(j + 1, Db, Da, b[j]);
-                dprev = d1;
-            }
-        } else {
-            // pairs (-1,0), (1,2), ..., (K-1,K): the lane's edge points pair
-            // with the neighbouring lanes' edge points, so u_{-2} and u_{K+1}
-            // are needed too
-            const T sl2 = from_left(xl2, s[K - 2]), sr2 = from_right(xr2, s[1]);
-            T el2 = T(0), er2 = T(0);
-            if constexpr (COMP) { el2 = from_left(yl2, e[K - 2]); er2 = from_right(yr2, e[1]); }
-            const auto dm2 = dif(sl, el, sl2, el2);                   // d_{-2}
-            const auto dm1 = dif(s[0], e[0], sl, el);                 // d_{-1}
-            const auto d0 = dif(s[1], e[1], s[0], e[0]);              // d_0
-            const auto dK1 = dif(sr, er, s[K - 1], e[K - 1]);         // d_{K-1}
-            const auto dK = dif(sr2, er2, sr, er);                    // d_K
-            const auto dK2 = dif(s[K - 1], e[K - 1], s[K - 2], e[K - 2]);  // d_{K-2}
-            upd(0, sd(dm1, d0), sd(dm2, dm1), bl);
-            auto dprev = d0;
-#pragma unroll
-            for (int q = 1; q < K / 2; ++q) {
-                const int j = 2 * q - 1;
-                const auto da = dif(s[j + 1], e[j + 1], s[j], e[j]); // d_j
-                const auto db = dif(s[j + 2], e[j + 2], s[j + 1], e[j + 1]);  // d_{j+1}
-                const T Da = sd(dprev, da), Db = sd(da, db);
-                upd(j, Da, Db, b[j + 1]);
-                upd(j + 1, Db, Da, b[j]);
-                dprev = db;
-            }
-            upd(K - 1, sd(dK2, dK1), sd(dK1, dK), br);
+        Lone<T> lone{T(0), T(0)};
+        if (WALL && singR)
+            lone = right_lone<T, K, COMP, SRC>(s, e, b, kS, xl, yl, gr_hi, gr_lo, dgr, cf, an);
+        ge_level<T, K, COMP, SRC, WALL, p>(s, e, b, bl, br, xl, xl2, xr, xr2, yl, yl2, yr,
+                                           yr2, cf, an, wlv, ft);
+        if (WALL && singR) {
+            put_at<T, K>(s, kS, tid == lS, lone.s);
+            if constexpr (COMP) put_at<T, K>(e, kS, tid == lS, lone.e);
         }
-    }
+        if (WALL && own_R) {
+            // wall first difference at the new level, accumulated in FP64
+            const double v = (double)get_at<T, K>(s, kS, T(0)) +
+                             (COMP ? (double)get_at<T, K>(e, kS, T(0)) : 0.0);
+            if (tid == lS) accR = accR + a.tau * (v - grn) / a.h;
+        }
+    });
+    accL = ft.accL;
 
     if (own_L && tid == 0) a.flux[0] = accL;
     if (own_R && tid == lS) a.flux[1] = accR;

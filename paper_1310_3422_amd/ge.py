@@ -60,6 +60,9 @@ _SIGS = {
     "ge_batch_plan": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GeBatchDesc)]),
     "ge_batch_destroy": (None, [_vp]),
     "ge_batch_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "ge_batch_state_elems": (_i64, [_vp]),
+    "ge_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_dbl), _vp]),
     "ge_solve_batch": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
 }
 
@@ -229,3 +232,90 @@ def unpack_state(u, n, precision):
         off = comp_offset(n)
         return a[:n].astype(np.float64) + a[off:off + n].astype(np.float64)
     return a[:n].astype(np.float64)
+
+
+class Batch:
+    """A ge_batch plan: independent rods advanced together in one persistent,
+    graph-captured launch.  Host arrays describe the rods; the packed state
+    lives in a device tensor (see ``pack_batch_state``)."""
+
+    def __init__(self, n, offsets, r, g_left, g_right, precision="fp32", tune=False):
+        self.n = np.ascontiguousarray(n, dtype=np.int64)
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.r = np.ascontiguousarray(r, dtype=np.float64)
+        self.g_left = np.ascontiguousarray(g_left, dtype=np.float64)
+        self.g_right = np.ascontiguousarray(g_right, dtype=np.float64)
+        self.precision = _prec(precision)
+        nr = self.n.size
+        if self.offsets.size != nr + 1 or any(a.size != nr for a in (self.r, self.g_left, self.g_right)):
+            raise ValueError("rod table arrays have inconsistent lengths")
+        c = lambda a: ctypes.c_void_p(a.ctypes.data)
+        self.desc = GeBatchDesc(nrods=nr, n=c(self.n), offsets=c(self.offsets), r=c(self.r),
+                                g_left=c(self.g_left), g_right=c(self.g_right),
+                                precision=self.precision, tune=1 if tune else 0)
+        h = _vp()
+        check(lib().ge_batch_plan(ctypes.byref(h), ctypes.byref(self.desc)))
+        self.handle = h
+        self.state_elems = int(lib().ge_batch_state_elems(h))
+        self.workspace_bytes = int(lib().ge_batch_workspace_bytes(h))
+
+    @classmethod
+    def from_inputs(cls, rb, precision="fp32", tune=False):
+        """From an ``inputs.RodBatch``."""
+        return cls(rb.n, rb.offsets, rb.r, rb.g_left, rb.g_right, precision, tune)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.ge_batch_destroy(h)
+            self.handle = None
+
+    def info(self):
+        nt, gr, est = _i32(), _i32(), _dbl()
+        ks = np.zeros(self.n.size, dtype=np.int32)
+        check(lib().ge_batch_info(self.handle, ctypes.byref(nt), ctypes.byref(gr),
+                                  ctypes.byref(est), ctypes.c_void_p(ks.ctypes.data)))
+        return {"ntasks": nt.value, "grid": gr.value, "est_us_per_level": est.value,
+                "rod_k": ks}
+
+    def new_workspace(self):
+        torch = _torch()
+        return torch.zeros(max(self.workspace_bytes, 256), dtype=torch.uint8, device="cuda")
+
+    def solve(self, u, step0, nsteps, workspace, stream=None):
+        torch = _torch()
+        Plan._check_tensor(u, self.state_elems, "u", state_dtype(self.precision))
+        if not workspace.is_cuda or workspace.numel() < self.workspace_bytes:
+            raise ValueError("workspace too small")
+        check(lib().ge_solve_batch(self.handle, _ptr(u), _ptr(workspace), int(step0),
+                                   int(nsteps), _stream_ptr(stream)))
+        return u
+
+
+def pack_batch_state(rb_u0, offsets, n, precision, device="cuda"):
+    """Host FP64 packed values (rods at ``offsets``) -> device state tensor in
+    the batch layout of the precision."""
+    torch = _torch()
+    p = _prec(precision)
+    u0 = np.ascontiguousarray(rb_u0, dtype=np.float64)
+    total = int(offsets[-1])
+    if p == GE_FP64:
+        return torch.from_numpy(u0[:total].copy()).to(device)
+    if p == GE_FP32:
+        return torch.from_numpy(u0[:total].astype(np.float32)).to(device)
+    off = comp_offset(total)
+    s = u0[:total].astype(np.float32)
+    e = (u0[:total] - s.astype(np.float64)).astype(np.float32)
+    buf = np.zeros(2 * off, dtype=np.float32)
+    buf[:total], buf[off:off + total] = s, e
+    return torch.from_numpy(buf).to(device)
+
+
+def unpack_batch_rod(u_host, offsets, n, i, precision):
+    """FP64 values of rod i from a host copy (numpy) of a batch state."""
+    p = _prec(precision)
+    a, b = int(offsets[i]), int(offsets[i]) + int(n[i])
+    if p == GE_FP32_COMP:
+        off = comp_offset(int(offsets[-1]))
+        return u_host[a:b].astype(np.float64) + u_host[off + a:off + b].astype(np.float64)
+    return u_host[a:b].astype(np.float64)

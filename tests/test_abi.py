@@ -160,3 +160,42 @@ def test_halo_of_depth_plus_one_is_enough_and_tight(depth, step0):
     # either cut is contaminated (starting on an odd level depth suffices)
     if step0 == 0:
         assert cut[lo - 1] != full[a + lo - 1] and cut[hi] != full[a + hi]
+
+
+def _batch_desc(n, offsets, r=None, gl=None, gr=None, precision=1, tune=0):
+    nr = len(n)
+    arrs = dict(n=np.asarray(n, np.int64), offsets=np.asarray(offsets, np.int64),
+                r=np.asarray(r if r is not None else [1.0] * nr, np.float64),
+                gl=np.asarray(gl if gl is not None else [0.0] * nr, np.float64),
+                gr=np.asarray(gr if gr is not None else [0.0] * nr, np.float64))
+    c = lambda a: ctypes.c_void_p(a.ctypes.data)
+    d = ge.GeBatchDesc(nrods=nr, n=c(arrs["n"]), offsets=c(arrs["offsets"]), r=c(arrs["r"]),
+                       g_left=c(arrs["gl"]), g_right=c(arrs["gr"]), precision=precision,
+                       tune=tune)
+    return d, arrs
+
+
+@pytest.mark.parametrize("case,status", [
+    (dict(n=[100, 0], offsets=[0, 100, 200]), ge.GE_ERR_INVALID),
+    (dict(n=[100, 50], offsets=[0, 98, 200]), ge.GE_ERR_INVALID),        # overlap
+    (dict(n=[100, 50], offsets=[0, 102, 200]), ge.GE_ERR_INVALID),       # not a multiple of 4
+    (dict(n=[100, 50], offsets=[0, 100, 200], r=[1.0, 0.0]), ge.GE_ERR_INVALID),
+    (dict(n=[100, 50], offsets=[0, 100, 200], r=[1.0, float("nan")]), ge.GE_ERR_NONFINITE),
+    (dict(n=[70000], offsets=[0, 70000]), ge.GE_ERR_UNSUPPORTED),        # above FP32 on-chip limit
+    (dict(n=[40000], offsets=[0, 40000], precision=0), ge.GE_ERR_UNSUPPORTED),
+    (dict(n=[100], offsets=[0, 100], precision=9), ge.GE_ERR_INVALID),
+])
+def test_batch_plan_rejects(case, status):
+    d, keep = _batch_desc(**case)
+    h = ctypes.c_void_p()
+    assert ge.lib().ge_batch_plan(ctypes.byref(h), ctypes.byref(d)) == status
+    assert not h.value
+
+
+def test_batch_null_arguments():
+    lib = ge.lib()
+    assert lib.ge_batch_plan(None, None) == ge.GE_ERR_INVALID
+    assert lib.ge_solve_batch(None, None, None, 0, 1, None) == ge.GE_ERR_INVALID
+    assert lib.ge_batch_state_elems(None) == -1
+    assert lib.ge_batch_workspace_bytes(None) == 0
+    lib.ge_batch_destroy(None)

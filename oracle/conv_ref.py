@@ -1,0 +1,149 @@
+"""FP64 CPU oracle of the learned 64-level propagator (the surrogate).
+
+TEST INFRASTRUCTURE ONLY: used by the tests to check the GPU network's
+forward pass and gradients; the GPU library never calls it.
+
+The network (a reading of the unstated details, see the design doc's list of
+readings): a 1D convolutional net over the n points of a rod, channels-last
+tensors x[b, w, c].
+
+    layer 1 : pre1 = conv(x, W1) + b1,           h1 = gelu(pre1)        (2 -> 64)
+    layer l : pre_l = conv(h_{l-1}, W_l) + b_l,  h_l = h_{l-1} + gelu(pre_l)
+              for l = 2..5                                             (64 -> 64)
+    layer 6 : out = conv(h5, W6) + b6                                    (64 -> 1)
+
+    conv(x, W)[b, w, o] = sum_{k=0..4} sum_i W[k, o, i] x[b, w + k - 2, i],
+    with x = 0 outside the rod (zero padding), gelu(z) = z Phi(z) with the
+    exact normal CDF Phi.
+
+Loss: mean over (b, w) of (out[b, w, 0] - t[b, w])^2.
+
+With ``bf16=True`` the forward and backward round to bfloat16 (round to
+nearest even) at the places where the GPU stores bfloat16: the input, the
+weights, every pre-activation and activation, the loss gradient, and every
+activation gradient; accumulation stays in FP64 here (FP32 on the GPU).
+"""
+import math
+
+import numpy as np
+
+LAYERS = [(2, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 1)]
+TAPS = 5
+
+
+def bf16(a):
+    """Round to the nearest bfloat16 (ties to even), via FP32."""
+    a32 = np.asarray(a, dtype=np.float32)
+    bits = a32.view(np.uint32).astype(np.uint64)
+    rounded = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16) << 16
+    out = rounded.astype(np.uint32).view(np.float32)
+    # keep NaN/Inf as they are
+    out = np.where(np.isfinite(a32), out, a32)
+    return out.astype(np.float64)
+
+
+def _erf(x):
+    return np.vectorize(math.erf, otypes=[np.float64])(x)
+
+
+def gelu(z):
+    return 0.5 * z * (1.0 + _erf(z / math.sqrt(2.0)))
+
+
+def gelu_grad(z):
+    phi = np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * phi
+
+
+def conv(x, w):
+    """x: (B, W, Ci), w: (5, Co, Ci) -> (B, W, Co), zero padding."""
+    B, Wn, Ci = x.shape
+    xp = np.zeros((B, Wn + TAPS - 1, Ci))
+    xp[:, 2:2 + Wn] = x
+    out = np.zeros((B, Wn, w.shape[1]))
+    for k in range(TAPS):
+        out += xp[:, k:k + Wn] @ w[k].T
+    return out
+
+
+def conv_input_grad(g, w):
+    """Gradient of conv(x, w) w.r.t. x for output gradient g (B, W, Co)."""
+    B, Wn, Co = g.shape
+    gp = np.zeros((B, Wn + TAPS - 1, Co))
+    gp[:, 2:2 + Wn] = g
+    out = np.zeros((B, Wn, w.shape[2]))
+    # x[w'] receives W[k] g[w' - k + 2]
+    for k in range(TAPS):
+        out += gp[:, TAPS - 1 - k:TAPS - 1 - k + Wn] @ w[k]
+    return out
+
+
+def conv_weight_grad(x, g):
+    """Gradient of sum(conv(x, w) * g) w.r.t. w: (5, Co, Ci)."""
+    B, Wn, Ci = x.shape
+    xp = np.zeros((B, Wn + TAPS - 1, Ci))
+    xp[:, 2:2 + Wn] = x
+    gw = np.zeros((TAPS, g.shape[2], Ci))
+    for k in range(TAPS):
+        gw[k] = np.einsum("bwo,bwi->oi", g, xp[:, k:k + Wn])
+    return gw
+
+
+def init_params(seed):
+    """He-style initialisation, seeded; the last layer starts small."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for li, (ci, co) in enumerate(LAYERS):
+        std = math.sqrt(2.0 / (TAPS * ci))
+        if li == len(LAYERS) - 1:
+            std *= 0.1
+        params.append((rng.standard_normal((TAPS, co, ci)) * std, np.zeros(co)))
+    return params
+
+
+def forward(params, x, bf=False):
+    """Returns (out, cache).  out: (B, W) FP64."""
+    r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
+    h = r(x)
+    cache = {"inputs": [], "pre": []}
+    for li, (w, b) in enumerate(params):
+        w = r(w)
+        cache["inputs"].append(h)
+        pre = conv(h, w) + b
+        if li == len(params) - 1:
+            cache["pre"].append(pre)
+            return pre[:, :, 0], cache
+        act = gelu(pre)
+        if li > 0:
+            act = h + act
+        cache["pre"].append(r(pre))
+        h = r(act)
+    raise AssertionError("unreachable")
+
+
+def loss_and_grads(params, x, t, bf=False):
+    """MSE loss and its gradients [(dW, db)] per layer."""
+    r = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
+    out, cache = forward(params, x, bf)
+    m = out.size
+    loss = float(np.mean((out - t) ** 2))
+    g = r((2.0 / m) * (out - t))[:, :, None]          # d loss / d out
+    grads = [None] * len(params)
+    nl = len(params)
+    g_h = None
+    for li in range(nl - 1, -1, -1):
+        w, b = params[li]
+        w = r(w)
+        x_in = cache["inputs"][li]
+        if li == nl - 1:
+            g_pre = g
+        else:
+            g_pre = r(g_h * gelu_grad(cache["pre"][li]))
+        grads[li] = (conv_weight_grad(x_in, g_pre), g_pre.sum(axis=(0, 1)))
+        if li == 0:
+            break
+        g_in = conv_input_grad(g_pre, w)
+        if 0 < li < nl - 1:
+            g_in = g_h + g_in           # residual path of layer li
+        g_h = r(g_in)
+    return loss, grads

@@ -1,0 +1,98 @@
+"""Pins of the FP64 oracle of the learned propagator (oracle/conv_ref.py):
+the convolution against its definition on a delta input, the backward pass
+against central finite differences, and bfloat16 rounding against values
+fixed by the format."""
+import numpy as np
+import pytest
+
+from oracle import conv_ref as cr
+
+
+def test_conv_delta_response_reproduces_the_taps():
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal((5, 3, 2))
+    x = np.zeros((1, 11, 2))
+    x[0, 5, 1] = 1.0
+    y = cr.conv(x, w)
+    # y[w] = sum_k W[k] x[w + k - 2]: the delta at 5 shows W[k] at w = 7 - k
+    for k in range(5):
+        np.testing.assert_array_equal(y[0, 7 - k], w[k][:, 1])
+    assert np.count_nonzero(y[0, :3]) == 0 and np.count_nonzero(y[0, 8:]) == 0
+
+
+def test_conv_zero_padding_at_rod_ends():
+    w = np.ones((5, 1, 1))
+    x = np.ones((1, 6, 1))
+    np.testing.assert_array_equal(cr.conv(x, w)[0, :, 0], [3, 4, 5, 5, 4, 3])
+
+
+def test_input_and_weight_gradients_are_adjoint():
+    """<conv(x, w), g> = <x, conv_input_grad(g, w)> = <w, conv_weight_grad(x, g)>."""
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, 13, 4))
+    w = rng.standard_normal((5, 3, 4))
+    g = rng.standard_normal((2, 13, 3))
+    lhs = np.sum(cr.conv(x, w) * g)
+    assert lhs == pytest.approx(np.sum(x * cr.conv_input_grad(g, w)), rel=1e-12)
+    assert lhs == pytest.approx(np.sum(w * cr.conv_weight_grad(x, g)), rel=1e-12)
+
+
+def test_gelu_values():
+    z = np.array([-2.0, 0.0, 1.0])
+    # z * Phi(z), Phi from the error function
+    np.testing.assert_allclose(cr.gelu(z), [-0.04550026389635842, 0.0, 0.8413447460685429],
+                               rtol=1e-14)
+    eps = 1e-6
+    fd = (cr.gelu(z + eps) - cr.gelu(z - eps)) / (2 * eps)
+    np.testing.assert_allclose(cr.gelu_grad(z), fd, rtol=1e-8)
+
+
+def _small_params(seed):
+    rng = np.random.default_rng(seed)
+    layers = [(2, 4), (4, 4), (4, 4), (4, 4), (4, 4), (4, 1)]
+    return [(rng.standard_normal((5, co, ci)) * 0.5, rng.standard_normal(co) * 0.1)
+            for ci, co in layers]
+
+
+def test_backward_matches_central_differences():
+    rng = np.random.default_rng(2)
+    params = _small_params(3)
+    x = rng.standard_normal((2, 9, 2))
+    t = rng.standard_normal((2, 9))
+    loss, grads = cr.loss_and_grads(params, x, t)
+    eps = 1e-5   # central-difference truncation ~eps^2, roundoff ~1e-16/eps
+    for li in range(len(params)):
+        w, b = params[li]
+        for _ in range(4):
+            idx = tuple(rng.integers(0, s) for s in w.shape)
+            wp = w.copy(); wp[idx] += eps
+            wm = w.copy(); wm[idx] -= eps
+            lp = cr.loss_and_grads(params[:li] + [(wp, b)] + params[li + 1:], x, t)[0]
+            lm = cr.loss_and_grads(params[:li] + [(wm, b)] + params[li + 1:], x, t)[0]
+            fd = (lp - lm) / (2 * eps)
+            assert grads[li][0][idx] == pytest.approx(fd, rel=1e-6, abs=1e-10), (li, idx)
+        j = rng.integers(0, b.size)
+        bp = b.copy(); bp[j] += eps
+        bm = b.copy(); bm[j] -= eps
+        fd = (cr.loss_and_grads(params[:li] + [(w, bp)] + params[li + 1:], x, t)[0] -
+              cr.loss_and_grads(params[:li] + [(w, bm)] + params[li + 1:], x, t)[0]) / (2 * eps)
+        assert grads[li][1][j] == pytest.approx(fd, rel=1e-6, abs=1e-10), (li, "bias")
+
+
+def test_bf16_rounding_values():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: ties go to the even 1.0;
+    # 1 + 3*2^-8 rounds up to 1 + 2^-6
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 3.1415926, 1e-40])
+    out = cr.bf16(v)
+    assert out[0] == 1.0
+    assert out[1] == 1.0
+    assert out[2] == 1.0 + 2 ** -6
+    assert out[3] == -2.5
+    assert out[4] == 3.140625
+    assert out[5] == np.float64(np.float32(1e-40)).item() or abs(out[5]) < 1e-38
+
+
+def test_parameter_count():
+    params = cr.init_params(0)
+    n = sum(w.size + b.size for w, b in params)
+    assert n == 83201

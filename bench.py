@@ -252,6 +252,23 @@ def main():
                                    0, 1)
             extra["fp32_compensated"] = {"updates_per_s": n * LEVELS / wc,
                                          "config": pc.config()}
+        # batch of 4096 independent rods (N log-uniform in [256, 65536],
+        # r in [0.25, 4], walls in [-1, 1], seed 3), 2000 levels, FP32, one
+        # persistent graph-captured launch
+        rb = inputs.rod_batch(seed=3, nrods=4096, align=4)
+        bt = ge.Batch.from_inputs(rb, "fp32")
+        ub = ge.pack_batch_state(rb.u0, rb.offsets, rb.n, "fp32")
+        wsb = bt.new_workspace()
+        with torch.cuda.stream(stream):
+            torch.cuda.synchronize()
+            wb, gb = time_runs(torch, stream,
+                               lambda: bt.solve(ub, 0, 2000, wsb, stream=stream), 1, 3)
+        info = bt.info()
+        extra["rod_batch_4096_fp32"] = {
+            "updates_per_s": float(rb.n.sum()) * 2000 * 3 / gb,
+            "ms_per_run": gb / 3 * 1e3, "tasks": info["ntasks"], "workgroups": info["grid"],
+            "rods": rb.nrods, "points": int(rb.n.sum()), "levels": 2000}
+        del ub, wsb, bt
         out["extra"] = extra
 
     if not args.no_cpu:

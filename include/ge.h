@@ -211,6 +211,61 @@ ge_status ge_batch_info(ge_batch_t batch, int32_t *ntasks, int32_t *grid,
 ge_status ge_solve_batch(ge_batch_t batch, void *u, void *workspace,
                          int64_t step0, int64_t nsteps, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned 64-level propagator (surrogate).  A 1D convolutional network over
+ * the points of a rod maps u at level m to a normalised increment; a jump is
+ *     u(m + 64) ~ u + 64 r s out,
+ * with s the RMS of the rod's second differences.  Layers (channels last,
+ * bfloat16 activations and weights, FP32 accumulation on the matrix cores):
+ * conv 2->64 + GELU; four residual layers h += GELU(conv 64->64); conv
+ * 64->1; kernel width 5, zero padding, exact-erf GELU.  Inputs: the second
+ * difference of u divided by s, and r mapped from [0.5, 2] to [-1, 1].
+ * Training minimises the mean squared error against the normalised
+ * increment (u(m + 64) - u(m)) / (64 r s) of the GE sweep, with Adam on
+ * FP32 master weights; every reduction has a fixed order, so a training run
+ * is reproducible bit for bit.
+ *
+ * Arrays: u, u64: device, batch x width floats (rods back to back, zero
+ * walls); r: device, batch floats.  width is a multiple of 128.
+ * ---------------------------------------------------------------------- */
+typedef struct ge_nn_s *ge_nn_t;
+
+/* Number of parameters (83201), in the flat layout used below: for each of
+ * the six layers, W[5][c_out][c_in] then b[c_out]. */
+int64_t ge_nn_param_count(void);
+
+/* Create a network for rods of `width` points and up to `max_batch` rods
+ * per call, with a seeded initialisation.  Allocates every device buffer
+ * the network needs (about 3.7 GB for 512 x 4096); later calls allocate
+ * nothing.  Errors: GE_ERR_INVALID, GE_ERR_NOMEM, GE_ERR_HIP. */
+ge_status ge_nn_create(ge_nn_t *out, int32_t width, int32_t max_batch, uint64_t seed);
+void ge_nn_destroy(ge_nn_t net);
+
+/* Copy the FP32 master parameters in (resets the optimiser) or out (host
+ * arrays of ge_nn_param_count() floats; synchronous). */
+ge_status ge_nn_set_params(ge_nn_t net, const float *host, int64_t count);
+ge_status ge_nn_get_params(ge_nn_t net, float *host, int64_t count);
+
+/* Network output (device, batch x width floats, the normalised increment)
+ * and the per-rod scale s (device, batch floats); either may be NULL. */
+ge_status ge_nn_forward(ge_nn_t net, const float *u, const float *r, int32_t batch,
+                        float *out, float *scale, void *stream);
+
+/* One 64-level jump: u_next = u + 64 r s out (device, batch x width). */
+ge_status ge_nn_jump(ge_nn_t net, const float *u, const float *r, int32_t batch,
+                     float *u_next, void *stream);
+
+/* Forward, loss and backward without an update: the mean squared error goes
+ * to *loss (device float, or NULL) and the gradient of every parameter is
+ * kept in the network (ge_nn_gradient copies it out). */
+ge_status ge_nn_grads(ge_nn_t net, const float *u, const float *u64, const float *r,
+                      int32_t batch, float *loss, void *stream);
+ge_status ge_nn_gradient(ge_nn_t net, float *grad /* device, param_count */, void *stream);
+
+/* ge_nn_grads followed by one Adam step (beta 0.9/0.999, eps 1e-8). */
+ge_status ge_nn_train_step(ge_nn_t net, const float *u, const float *u64, const float *r,
+                           int32_t batch, float lr, float *loss, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,13 @@ tensors x[b, w, c].
 
 Loss: mean over (b, w) of (out[b, w, 0] - t[b, w])^2.
 
+Around the network (``features``, ``target``, ``jump``): the input of a
+rod u (zero walls) is its second difference D_i = u_{i-1} - 2 u_i + u_{i+1}
+scaled by its root mean square s, and the mesh ratio mapped from [0.5, 2]
+to [-1, 1]; the network predicts the 64-level increment in units of 64 r s,
+which is about one explicit step of length 64 tau (u_t = u_xx gives
+du ~ 64 tau u_xx = 64 r D).
+
 With ``bf16=True`` the forward and backward round to bfloat16 (round to
 nearest even) at the places where the GPU stores bfloat16: the input, the
 weights, every pre-activation and activation, the loss gradient, and every
@@ -87,6 +94,30 @@ def conv_weight_grad(x, g):
     for k in range(TAPS):
         gw[k] = np.einsum("bwo,bwi->oi", g, xp[:, k:k + Wn])
     return gw
+
+
+def features(u, r):
+    """u: (B, W) rod values, r: (B,) mesh ratios -> (x (B, W, 2), s (B,))."""
+    u = np.asarray(u, dtype=np.float64)
+    up = np.pad(u, ((0, 0), (1, 1)))
+    d = up[:, :-2] - 2.0 * up[:, 1:-1] + up[:, 2:]
+    s = np.sqrt(np.mean(d * d, axis=1))
+    x = np.empty(u.shape + (2,))
+    x[:, :, 0] = d / s[:, None]
+    x[:, :, 1] = ((np.asarray(r, dtype=np.float64) - 1.25) / 0.75)[:, None]
+    return x, s
+
+
+def target(u, u64, r, s):
+    """Normalised 64-level increment (u64 - u) / (64 r s)."""
+    r = np.asarray(r, dtype=np.float64)
+    return (np.asarray(u64, np.float64) - np.asarray(u, np.float64)) / (64.0 * r * s)[:, None]
+
+
+def jump(u, out, r, s):
+    """u + 64 r s out: the surrogate's 64-level step."""
+    r = np.asarray(r, dtype=np.float64)
+    return np.asarray(u, np.float64) + (64.0 * r * s)[:, None] * out
 
 
 def init_params(seed):

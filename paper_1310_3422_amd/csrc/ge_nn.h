@@ -1,0 +1,54 @@
+// Internal interface of the surrogate network kernels (ge_nn.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ge {
+namespace nn {
+
+enum Epi : int { kEpiGelu = 0, kEpiGeluRes = 1, kEpiOut = 2, kEpiBwd = 3 };
+
+struct ConvArgs {
+    const void *x;        // bf16 [batch][width][cin]
+    const void *w;        // bf16 [5][cout][cin]
+    const float *bias;    // [cout] or null
+    int width;            // points per rod, a multiple of 128
+    void *pre_out;        // bf16 [..][cout]  (kEpiGelu*)
+    void *act_out;        // bf16 [..][cout]  (kEpiGelu*)
+    float *out_f32;       // f32 [batch][width] (kEpiOut)
+    const void *res_in;   // bf16 [..][cout]  (kEpiBwd, or null)
+    const void *pre_in;   // bf16 [..][cout]  (kEpiBwd)
+    void *gh_out;         // bf16 [..][cout]  (kEpiBwd, or null)
+    void *gp_out;         // bf16 [..][cout]  (kEpiBwd)
+};
+
+struct WgradArgs {
+    const void *x;        // bf16 [batch][width][cin]
+    const void *g;        // bf16 [batch][width][cout]
+    float *part;          // per-workgroup partials
+    int width;
+    int batch;
+};
+
+constexpr int kMaxWgradBlocks = 256;
+
+hipError_t launch_conv(int cin, int cout, int epi, const ConvArgs &a, int batch, hipStream_t s);
+hipError_t launch_wgrad(int cin, int cout, const WgradArgs &a, int blocks, hipStream_t s);
+hipError_t launch_wgrad_reduce(const float *part, int nblocks, int cinp, int coutp, int ci,
+                               int co, float *grad, hipStream_t s);
+hipError_t launch_features(const float *u, const float *r, int W, int batch, void *x,
+                           float *scale, hipStream_t s);
+hipError_t launch_loss(const float *out, const float *u, const float *u64, const float *r,
+                       const float *scale, int W, int batch, void *g, float *part, float *loss,
+                       hipStream_t s);
+int loss_blocks(int W, int batch);
+hipError_t launch_jump(const float *u, const float *out, const float *r, const float *scale,
+                       int W, int batch, float *u_next, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                       float b1, float b2, float eps, int step, hipStream_t s);
+hipError_t launch_pack(const float *wm, const float *bm, int ci, int co, int cip, int cop,
+                       int cod, void *wf, float *bf, void *wd, hipStream_t s);
+
+}  // namespace nn
+}  // namespace ge

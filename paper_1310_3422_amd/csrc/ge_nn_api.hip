@@ -1,0 +1,369 @@
+// C ABI of the learned 64-level propagator: a network object that owns its
+// parameters, Adam state and activation buffers (allocated once, at
+// creation), and the sequences of kernels for a forward pass, a jump and a
+// training step.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ge.h"
+#include "ge_internal.h"
+#include "ge_nn.h"
+
+namespace {
+
+using namespace ge::nn;
+
+struct Layer {
+    int ci, co;      // real channels
+    int cip, cop;    // padded forward channels (input, output)
+    int cod;         // padded channels of the gradient entering the layer (its output)
+    int64_t off;     // offset of W[5][co][ci] then b[co] in the flat parameter array
+};
+
+// flat layout: for each layer in order, W[5][co][ci] then b[co]
+constexpr int64_t kOff1 = 5 * 64 * 2 + 64;
+constexpr int64_t kOffH = 5 * 64 * 64 + 64;
+const Layer kLayers[6] = {
+    {2, 64, 32, 64, 64, 0},
+    {64, 64, 64, 64, 64, kOff1},
+    {64, 64, 64, 64, 64, kOff1 + kOffH},
+    {64, 64, 64, 64, 64, kOff1 + 2 * kOffH},
+    {64, 64, 64, 64, 64, kOff1 + 3 * kOffH},
+    {64, 1, 64, 16, 32, kOff1 + 4 * kOffH},
+};
+
+int64_t layer_params(const Layer &l) { return 5LL * l.co * l.ci + l.co; }
+
+int64_t total_params()
+{
+    int64_t n = 0;
+    for (const Layer &l : kLayers) n += layer_params(l);
+    return n;
+}
+
+ge_status fail(ge_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+ge_status fail(ge_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    ge::vset_error(st, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+// splitmix64 stream and Box-Muller normals for the seeded initialisation
+struct Rng {
+    uint64_t s;
+    uint64_t next()
+    {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    double uniform() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+    double normal()
+    {
+        const double u1 = uniform(), u2 = uniform();
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+    }
+};
+
+}  // namespace
+
+struct ge_nn_s {
+    int width, max_batch;
+    int64_t nparam;
+    float *p, *g, *m, *v;           // FP32 master parameters, gradient, Adam moments
+    void *wf[6], *wd[6];            // packed bf16 weights (forward, input-gradient)
+    float *bf[6];                   // padded biases
+    void *x;                        // bf16 [B][W][32] features
+    void *pre[5], *h[5];            // bf16 [B][W][64]
+    float *out, *scale, *loss_part, *wpart;
+    void *gl;                       // bf16 [B][W][32] loss gradient
+    void *gh, *gp[2];               // bf16 [B][W][64]
+    int step;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+void free_nn(ge_nn_s *n)
+{
+    if (!n) return;
+    for (void *p : n->allocs) (void)hipFree(p);
+    delete n;
+}
+
+template <typename T>
+bool dalloc(ge_nn_s *n, T **p, size_t bytes)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) return false;
+    n->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return true;
+}
+
+hipError_t pack_all(ge_nn_s *n, hipStream_t s)
+{
+    for (int l = 0; l < 6; ++l) {
+        const Layer &L = kLayers[l];
+        const float *wm = n->p + L.off;
+        const float *bm = wm + 5LL * L.co * L.ci;
+        hipError_t e = launch_pack(wm, bm, L.ci, L.co, L.cip, L.cop, L.cod, n->wf[l], n->bf[l],
+                                   l > 0 ? n->wd[l] : nullptr, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+ge_status check_io(ge_nn_s *n, int batch, const char *what)
+{
+    if (!n) return fail(GE_ERR_INVALID, "%s: network is NULL", what);
+    if (batch < 1 || batch > n->max_batch)
+        return fail(GE_ERR_INVALID, "%s: batch %d outside [1, %d]", what, batch, n->max_batch);
+    return GE_OK;
+}
+
+hipError_t forward(ge_nn_s *n, const float *u, const float *r, int batch, hipStream_t s)
+{
+    const int W = n->width;
+    hipError_t e = launch_features(u, r, W, batch, n->x, n->scale, s);
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < 6; ++l) {
+        const Layer &L = kLayers[l];
+        ConvArgs a{};
+        a.x = l == 0 ? n->x : n->h[l - 1];
+        a.w = n->wf[l];
+        a.bias = n->bf[l];
+        a.width = W;
+        if (l < 5) {
+            a.pre_out = n->pre[l];
+            a.act_out = n->h[l];
+        } else {
+            a.out_f32 = n->out;
+        }
+        const int epi = l == 0 ? kEpiGelu : (l < 5 ? kEpiGeluRes : kEpiOut);
+        e = launch_conv(L.cip, L.cop, epi, a, batch, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int wgrad_blocks(ge_nn_s *n, int batch)
+{
+    const int64_t nseg = (int64_t)batch * (n->width / 128);
+    return (int)std::min<int64_t>(kMaxWgradBlocks, nseg);
+}
+
+// loss gradient already in n->gl; fills n->g (flat parameter gradient)
+hipError_t backward(ge_nn_s *n, int batch, hipStream_t s)
+{
+    const int W = n->width;
+    const int nb = wgrad_blocks(n, batch);
+    // layer 6: weight gradient from h5 and the loss gradient; input gradient
+    {
+        const Layer &L = kLayers[5];
+        WgradArgs wa{n->h[4], n->gl, n->wpart, W, batch};
+        hipError_t e = launch_wgrad(64, 32, wa, nb, s);
+        if (e == hipSuccess) e = launch_wgrad_reduce(n->wpart, nb, 64, 32, L.ci, L.co, n->g + L.off, s);
+        if (e != hipSuccess) return e;
+        ConvArgs a{};
+        a.x = n->gl;
+        a.w = n->wd[5];
+        a.width = W;
+        a.res_in = nullptr;
+        a.pre_in = n->pre[4];
+        a.gh_out = n->gh;
+        a.gp_out = n->gp[0];
+        e = launch_conv(32, 64, kEpiBwd, a, batch, s);
+        if (e != hipSuccess) return e;
+    }
+    int cur = 0;
+    for (int l = 4; l >= 1; --l) {
+        const Layer &L = kLayers[l];
+        WgradArgs wa{n->h[l - 1], n->gp[cur], n->wpart, W, batch};
+        hipError_t e = launch_wgrad(64, 64, wa, nb, s);
+        if (e == hipSuccess) e = launch_wgrad_reduce(n->wpart, nb, 64, 64, L.ci, L.co, n->g + L.off, s);
+        if (e != hipSuccess) return e;
+        ConvArgs a{};
+        a.x = n->gp[cur];
+        a.w = n->wd[l];
+        a.width = W;
+        a.res_in = n->gh;             // residual path of layer l (read and rewritten in place)
+        a.pre_in = n->pre[l - 1];
+        a.gh_out = n->gh;
+        a.gp_out = n->gp[1 - cur];
+        e = launch_conv(64, 64, kEpiBwd, a, batch, s);
+        if (e != hipSuccess) return e;
+        cur = 1 - cur;
+    }
+    const Layer &L = kLayers[0];
+    WgradArgs wa{n->x, n->gp[cur], n->wpart, W, batch};
+    hipError_t e = launch_wgrad(32, 64, wa, nb, s);
+    if (e == hipSuccess) e = launch_wgrad_reduce(n->wpart, nb, 32, 64, L.ci, L.co, n->g + L.off, s);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t ge_nn_param_count(void) { return total_params(); }
+
+ge_status ge_nn_create(ge_nn_t *out, int32_t width, int32_t max_batch, uint64_t seed)
+{
+    if (!out) return fail(GE_ERR_INVALID, "ge_nn_create: out is NULL");
+    *out = nullptr;
+    if (width < 128 || width % 128 != 0 || width > (1 << 20))
+        return fail(GE_ERR_INVALID, "ge_nn_create: width %d must be a positive multiple of 128",
+                    width);
+    if (max_batch < 1 || (int64_t)max_batch * width > (1LL << 26))
+        return fail(GE_ERR_INVALID, "ge_nn_create: max_batch %d out of range", max_batch);
+    ge_nn_s *n = new (std::nothrow) ge_nn_s();
+    if (!n) return fail(GE_ERR_NOMEM, "ge_nn_create: out of host memory");
+    n->width = width;
+    n->max_batch = max_batch;
+    n->nparam = total_params();
+    const size_t M = (size_t)max_batch * width;
+    bool ok = dalloc(n, &n->p, n->nparam * 4) && dalloc(n, &n->g, n->nparam * 4) &&
+              dalloc(n, &n->m, n->nparam * 4) && dalloc(n, &n->v, n->nparam * 4) &&
+              dalloc(n, &n->x, M * 32 * 2) && dalloc(n, &n->out, M * 4) &&
+              dalloc(n, &n->scale, (size_t)max_batch * 4) &&
+              dalloc(n, &n->loss_part, ((M + 255) / 256 + 1) * 4) &&
+              dalloc(n, &n->wpart, (size_t)kMaxWgradBlocks * (5 * 64 * 64 + 64) * 4) &&
+              dalloc(n, &n->gl, M * 32 * 2) && dalloc(n, &n->gh, M * 64 * 2) &&
+              dalloc(n, &n->gp[0], M * 64 * 2) && dalloc(n, &n->gp[1], M * 64 * 2);
+    for (int l = 0; ok && l < 5; ++l)
+        ok = dalloc(n, &n->pre[l], M * 64 * 2) && dalloc(n, &n->h[l], M * 64 * 2);
+    for (int l = 0; ok && l < 6; ++l) {
+        const Layer &L = kLayers[l];
+        ok = dalloc(n, &n->wf[l], 5LL * L.cop * L.cip * 2) && dalloc(n, &n->bf[l], L.cop * 4);
+        if (ok && l > 0) ok = dalloc(n, &n->wd[l], 5LL * L.cip * L.cod * 2);
+    }
+    if (!ok) {
+        free_nn(n);
+        return fail(GE_ERR_NOMEM, "ge_nn_create: device buffers for batch %d x width %d",
+                    max_batch, width);
+    }
+    // seeded He initialisation (the last layer starts small), zero biases
+    std::vector<float> h(n->nparam, 0.f);
+    Rng rng{seed};
+    for (int l = 0; l < 6; ++l) {
+        const Layer &L = kLayers[l];
+        double sd = std::sqrt(2.0 / (5.0 * L.ci));
+        if (l == 5) sd *= 0.1;
+        for (int64_t i = 0; i < 5LL * L.co * L.ci; ++i) h[L.off + i] = (float)(rng.normal() * sd);
+    }
+    hipError_t e = hipMemcpy(n->p, h.data(), n->nparam * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(n->m, 0, n->nparam * 4);
+    if (e == hipSuccess) e = hipMemset(n->v, 0, n->nparam * 4);
+    if (e == hipSuccess) e = pack_all(n, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_nn(n);
+        return fail(GE_ERR_HIP, "ge_nn_create: %s", hipGetErrorString(e));
+    }
+    *out = n;
+    return GE_OK;
+}
+
+void ge_nn_destroy(ge_nn_t n) { free_nn(n); }
+
+ge_status ge_nn_set_params(ge_nn_t n, const float *host, int64_t count)
+{
+    if (!n || !host) return fail(GE_ERR_INVALID, "ge_nn_set_params: NULL argument");
+    if (count != n->nparam)
+        return fail(GE_ERR_INVALID, "ge_nn_set_params: %lld values, need %lld", (long long)count,
+                    (long long)n->nparam);
+    hipError_t e = hipMemcpy(n->p, host, count * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(n->m, 0, count * 4);
+    if (e == hipSuccess) e = hipMemset(n->v, 0, count * 4);
+    if (e == hipSuccess) e = pack_all(n, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    n->step = 0;
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_set_params: %s", hipGetErrorString(e));
+}
+
+ge_status ge_nn_get_params(ge_nn_t n, float *host, int64_t count)
+{
+    if (!n || !host) return fail(GE_ERR_INVALID, "ge_nn_get_params: NULL argument");
+    if (count != n->nparam)
+        return fail(GE_ERR_INVALID, "ge_nn_get_params: %lld values, need %lld", (long long)count,
+                    (long long)n->nparam);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(host, n->p, count * 4, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_get_params: %s", hipGetErrorString(e));
+}
+
+ge_status ge_nn_forward(ge_nn_t n, const float *u, const float *r, int32_t batch, float *out,
+                        float *scale, void *stream)
+{
+    ge_status st = check_io(n, batch, "ge_nn_forward");
+    if (st != GE_OK) return st;
+    if (!u || !r) return fail(GE_ERR_INVALID, "ge_nn_forward: u and r must be given");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = forward(n, u, r, batch, s);
+    const size_t M = (size_t)batch * n->width;
+    if (e == hipSuccess && out) e = hipMemcpyAsync(out, n->out, M * 4, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && scale)
+        e = hipMemcpyAsync(scale, n->scale, (size_t)batch * 4, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_forward: %s", hipGetErrorString(e));
+}
+
+ge_status ge_nn_jump(ge_nn_t n, const float *u, const float *r, int32_t batch, float *u_next,
+                     void *stream)
+{
+    ge_status st = check_io(n, batch, "ge_nn_jump");
+    if (st != GE_OK) return st;
+    if (!u || !r || !u_next) return fail(GE_ERR_INVALID, "ge_nn_jump: NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = forward(n, u, r, batch, s);
+    if (e == hipSuccess) e = launch_jump(u, n->out, r, n->scale, n->width, batch, u_next, s);
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_jump: %s", hipGetErrorString(e));
+}
+
+ge_status ge_nn_grads(ge_nn_t n, const float *u, const float *u64, const float *r, int32_t batch,
+                      float *loss, void *stream)
+{
+    ge_status st = check_io(n, batch, "ge_nn_grads");
+    if (st != GE_OK) return st;
+    if (!u || !u64 || !r) return fail(GE_ERR_INVALID, "ge_nn_grads: NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = forward(n, u, r, batch, s);
+    if (e == hipSuccess)
+        e = launch_loss(n->out, u, u64, r, n->scale, n->width, batch, n->gl, n->loss_part, loss, s);
+    if (e == hipSuccess) e = backward(n, batch, s);
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_grads: %s", hipGetErrorString(e));
+}
+
+ge_status ge_nn_gradient(ge_nn_t n, float *grad, void *stream)
+{
+    if (!n || !grad) return fail(GE_ERR_INVALID, "ge_nn_gradient: NULL argument");
+    hipError_t e = hipMemcpyAsync(grad, n->g, n->nparam * 4, hipMemcpyDeviceToDevice,
+                                  static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_gradient: %s", hipGetErrorString(e));
+}
+
+ge_status ge_nn_train_step(ge_nn_t n, const float *u, const float *u64, const float *r,
+                           int32_t batch, float lr, float *loss, void *stream)
+{
+    if (!(lr > 0.f) || !std::isfinite(lr))
+        return fail(GE_ERR_INVALID, "ge_nn_train_step: learning rate must be positive");
+    ge_status st = ge_nn_grads(n, u, u64, r, batch, loss, stream);
+    if (st != GE_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    n->step += 1;
+    hipError_t e = launch_adam(n->p, n->g, n->m, n->v, n->nparam, lr, 0.9f, 0.999f, 1e-8f,
+                               n->step, s);
+    if (e == hipSuccess) e = pack_all(n, s);
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_train_step: %s", hipGetErrorString(e));
+}
+
+}  // extern "C"

@@ -64,6 +64,16 @@ _SIGS = {
     "ge_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                      ctypes.POINTER(_dbl), _vp]),
     "ge_solve_batch": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
+    "ge_nn_param_count": (_i64, []),
+    "ge_nn_create": (ctypes.c_int, [ctypes.POINTER(_vp), _i32, _i32, ctypes.c_uint64]),
+    "ge_nn_destroy": (None, [_vp]),
+    "ge_nn_set_params": (ctypes.c_int, [_vp, _vp, _i64]),
+    "ge_nn_get_params": (ctypes.c_int, [_vp, _vp, _i64]),
+    "ge_nn_forward": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "ge_nn_jump": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "ge_nn_grads": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp]),
+    "ge_nn_gradient": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ge_nn_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, _vp, _vp]),
 }
 
 
@@ -319,3 +329,77 @@ def unpack_batch_rod(u_host, offsets, n, i, precision):
         off = comp_offset(int(offsets[-1]))
         return u_host[a:b].astype(np.float64) + u_host[off + a:off + b].astype(np.float64)
     return u_host[a:b].astype(np.float64)
+
+
+class Net:
+    """The learned 64-level propagator (ge_nn_*): parameters and buffers live
+    on the device; tensors passed in are float32 CUDA tensors, rods back to
+    back (batch x width)."""
+
+    def __init__(self, width=4096, max_batch=512, seed=4):
+        self.width, self.max_batch = int(width), int(max_batch)
+        h = _vp()
+        check(lib().ge_nn_create(ctypes.byref(h), self.width, self.max_batch, int(seed)))
+        self.handle = h
+        self.nparam = int(lib().ge_nn_param_count())
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.ge_nn_destroy(h)
+            self.handle = None
+
+    def _check(self, t, numel, name):
+        torch = _torch()
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != numel:
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of {numel} values")
+
+    def params(self):
+        out = np.zeros(self.nparam, dtype=np.float32)
+        check(lib().ge_nn_get_params(self.handle, ctypes.c_void_p(out.ctypes.data), self.nparam))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        check(lib().ge_nn_set_params(self.handle, ctypes.c_void_p(p.ctypes.data), p.size))
+
+    def forward(self, u, r, stream=None):
+        torch = _torch()
+        b = r.numel()
+        self._check(u, b * self.width, "u")
+        self._check(r, b, "r")
+        out = torch.empty(b * self.width, dtype=torch.float32, device=u.device)
+        scale = torch.empty(b, dtype=torch.float32, device=u.device)
+        check(lib().ge_nn_forward(self.handle, _ptr(u), _ptr(r), b, _ptr(out), _ptr(scale),
+                                  _stream_ptr(stream)))
+        return out, scale
+
+    def jump(self, u, r, out=None, stream=None):
+        torch = _torch()
+        b = r.numel()
+        self._check(u, b * self.width, "u")
+        self._check(r, b, "r")
+        if out is None:
+            out = torch.empty_like(u)
+        check(lib().ge_nn_jump(self.handle, _ptr(u), _ptr(r), b, _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def grads(self, u, u64, r, stream=None):
+        """(loss, flat gradient) for one batch, without an update."""
+        torch = _torch()
+        b = r.numel()
+        for t, name in ((u, "u"), (u64, "u64")):
+            self._check(t, b * self.width, name)
+        loss = torch.zeros(1, dtype=torch.float32, device=u.device)
+        g = torch.empty(self.nparam, dtype=torch.float32, device=u.device)
+        check(lib().ge_nn_grads(self.handle, _ptr(u), _ptr(u64), _ptr(r), b, _ptr(loss),
+                                _stream_ptr(stream)))
+        check(lib().ge_nn_gradient(self.handle, _ptr(g), _stream_ptr(stream)))
+        return loss, g
+
+    def train_step(self, u, u64, r, lr, loss=None, stream=None):
+        b = r.numel()
+        for t, name in ((u, "u"), (u64, "u64")):
+            self._check(t, b * self.width, name)
+        check(lib().ge_nn_train_step(self.handle, _ptr(u), _ptr(u64), _ptr(r), b, float(lr),
+                                     _ptr(loss), _stream_ptr(stream)))

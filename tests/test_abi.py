@@ -199,3 +199,30 @@ def test_batch_null_arguments():
     assert lib.ge_batch_state_elems(None) == -1
     assert lib.ge_batch_workspace_bytes(None) == 0
     lib.ge_batch_destroy(None)
+
+
+def test_nn_parameter_count_and_create_rejects():
+    lib = ge.lib()
+    assert lib.ge_nn_param_count() == 83201
+    h = ctypes.c_void_p()
+    assert lib.ge_nn_create(None, 4096, 4, 0) == ge.GE_ERR_INVALID
+    for width, batch in [(0, 1), (100, 1), (4096 + 64, 1), (4096, 0), (4096, 1 << 20)]:
+        assert lib.ge_nn_create(ctypes.byref(h), width, batch, 0) == ge.GE_ERR_INVALID, (width, batch)
+        assert h.value is None
+    assert b"multiple of 128" in lib.ge_last_error() or b"out of range" in lib.ge_last_error()
+
+
+def test_nn_calls_reject_null_network():
+    lib = ge.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.ge_nn_forward(None, fake, fake, 1, fake, fake, None) == ge.GE_ERR_INVALID
+    assert lib.ge_nn_jump(None, fake, fake, 1, fake, None) == ge.GE_ERR_INVALID
+    assert lib.ge_nn_grads(None, fake, fake, fake, 1, None, None) == ge.GE_ERR_INVALID
+    assert lib.ge_nn_train_step(None, fake, fake, fake, 1, ctypes.c_float(1e-3), None,
+                                None) == ge.GE_ERR_INVALID
+    assert lib.ge_nn_train_step(None, fake, fake, fake, 1, ctypes.c_float(-1.0), None,
+                                None) == ge.GE_ERR_INVALID
+    assert lib.ge_nn_set_params(None, None, 0) == ge.GE_ERR_INVALID
+    assert lib.ge_nn_get_params(None, None, 0) == ge.GE_ERR_INVALID
+    assert lib.ge_nn_gradient(None, None, None) == ge.GE_ERR_INVALID
+    lib.ge_nn_destroy(None)

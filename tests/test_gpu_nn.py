@@ -1,0 +1,179 @@
+"""GPU parity of the learned 64-level propagator (ge_nn_*) with its FP64
+oracle run on the same bfloat16-rounded operands: the forward pass, the loss
+and every layer's gradient, the Adam update, determinism of training, and
+that training lowers the loss."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import conv_ref as cr
+from paper_1310_3422_amd import ge, inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# Bound on the mismatch from bfloat16 rounding decisions that the FP32
+# accumulation (order differs from the FP64 oracle) flips: a flip moves one
+# stored value by one bf16 ulp (2^-8 relative) and happens for a fraction of
+# about 1e-6 / 2^-8 of the values, so tensors differ by about 1e-4 in
+# relative L2; the bar keeps a margin of 20.
+BF16_FLIP_TOL = 2e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    ge.lib()
+
+
+def rel_l2(x, y):
+    return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
+
+
+def flatten(params):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params])
+
+
+def unflatten(flat):
+    out, o = [], 0
+    for ci, co in cr.LAYERS:
+        nw = 5 * co * ci
+        out.append((flat[o:o + nw].reshape(5, co, ci), flat[o + nw:o + nw + co]))
+        o += nw + co
+    assert o == flat.size
+    return out
+
+
+def fp32_params(seed):
+    """Oracle initialisation with small random biases, rounded to FP32 (the
+    GPU keeps FP32 master parameters)."""
+    rng = np.random.default_rng(seed + 100)
+    params = [(w, 0.05 * rng.standard_normal(b.size)) for w, b in cr.init_params(seed)]
+    return unflatten(flatten(params).astype(np.float32).astype(np.float64))
+
+
+def rods(seed, nrods, width, levels=64):
+    """Seeded surrogate rods (FP32) and their FP64 GE state after 64 levels,
+    rounded to FP32."""
+    r, u0 = inputs.surrogate_rods(seed, nrods, n=width)
+    u = u0.astype(np.float32)
+    u64 = np.stack([oracle.step_n(u[i].astype(np.float64), r[i], levels) for i in range(nrods)])
+    return r.astype(np.float32), u, u64.astype(np.float32)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32).ravel()).cuda()
+
+
+def make_net(width, max_batch, params):
+    net = ge.Net(width=width, max_batch=max_batch, seed=1)
+    net.set_params(flatten(params).astype(np.float32))
+    return net
+
+
+def test_parameter_round_trip():
+    net = ge.Net(width=256, max_batch=2, seed=9)
+    assert net.nparam == 83201
+    p = net.params()
+    assert np.isfinite(p).all() and np.count_nonzero(p) > 80000
+    q = np.arange(p.size, dtype=np.float32) * 1e-6
+    net.set_params(q)
+    np.testing.assert_array_equal(net.params(), q)
+
+
+@pytest.mark.parametrize("width,batch", [(512, 3), (4096, 1)])
+def test_forward_matches_oracle(width, batch):
+    params = fp32_params(7)
+    r, u, _ = rods(40, batch, width, levels=0)
+    net = make_net(width, batch, params)
+    out, scale = net.forward(dev(u), dev(r))
+    torch.cuda.synchronize()
+    x, s = cr.features(u.astype(np.float64), r.astype(np.float64))
+    np.testing.assert_allclose(scale.cpu().numpy(), s, rtol=1e-5)
+    want, _ = cr.forward(params, x, bf=True)
+    got = out.cpu().numpy().reshape(batch, width)
+    assert rel_l2(got, want) < BF16_FLIP_TOL
+    # and the rounding points matter less than the flip bar times 20
+    exact, _ = cr.forward(params, x, bf=False)
+    assert rel_l2(got, exact) < 20 * BF16_FLIP_TOL
+
+
+def test_jump_applies_the_scaled_increment():
+    width, batch = 512, 2
+    params = fp32_params(8)
+    r, u, _ = rods(41, batch, width, levels=0)
+    net = make_net(width, batch, params)
+    out, scale = net.forward(dev(u), dev(r))
+    un = net.jump(dev(u), dev(r))
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().reshape(batch, width).astype(np.float64)
+    sc = scale.cpu().numpy().astype(np.float64)
+    want = u.astype(np.float64) + 64.0 * r.astype(np.float64)[:, None] * sc[:, None] * o
+    np.testing.assert_allclose(un.cpu().numpy().reshape(batch, width), want, rtol=0,
+                               atol=4e-7 * np.abs(u).max())
+
+
+def test_loss_and_gradients_match_oracle():
+    width, batch = 512, 3
+    params = fp32_params(11)
+    r, u, u64 = rods(42, batch, width)
+    net = make_net(width, batch, params)
+    loss, g = net.grads(dev(u), dev(u64), dev(r))
+    torch.cuda.synchronize()
+    x, s = cr.features(u.astype(np.float64), r.astype(np.float64))
+    t = cr.target(u, u64, r, s)
+    want_loss, want = cr.loss_and_grads(params, x, t, bf=True)
+    assert float(loss.cpu()[0]) == pytest.approx(want_loss, rel=BF16_FLIP_TOL)
+    got = unflatten(g.cpu().numpy().astype(np.float64))
+    for li, ((gw, gb), (ww, wb)) in enumerate(zip(got, want)):
+        assert rel_l2(gw, ww) < BF16_FLIP_TOL, ("weights", li, rel_l2(gw, ww))
+        assert rel_l2(gb, wb) < BF16_FLIP_TOL, ("bias", li, rel_l2(gb, wb))
+
+
+def test_adam_update_of_the_measured_gradient():
+    width, batch = 256, 2
+    params = fp32_params(12)
+    r, u, u64 = rods(43, batch, width)
+    net = make_net(width, batch, params)
+    p0 = net.params()
+    _, g = net.grads(dev(u), dev(u64), dev(r))
+    g = g.cpu().numpy()
+    lr = 1e-3
+    net.train_step(dev(u), dev(u64), dev(r), lr)
+    torch.cuda.synchronize()
+    p1 = net.params()
+    # first Adam step (bias-corrected): m = g, v = g^2, p -= lr g / (|g| + eps)
+    g64 = g.astype(np.float64)
+    want = p0.astype(np.float64) - lr * g64 / (np.abs(g64) + 1e-8)
+    np.testing.assert_allclose(p1, want, rtol=0, atol=1e-6 * lr + 1e-7 * np.abs(want).max())
+
+
+def test_training_is_deterministic():
+    width, batch = 256, 4
+    r, u, u64 = rods(44, batch, width)
+    nets = [ge.Net(width=width, max_batch=batch, seed=5) for _ in range(2)]
+    for net in nets:
+        for _ in range(5):
+            net.train_step(dev(u), dev(u64), dev(r), 1e-3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(nets[0].params(), nets[1].params())
+
+
+def test_training_lowers_the_loss():
+    width, batch = 512, 8
+    r, u, u64 = rods(45, batch, width)
+    net = ge.Net(width=width, max_batch=batch, seed=6)
+    ud, u64d, rd = dev(u), dev(u64), dev(r)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    first = None
+    for it in range(300):
+        net.train_step(ud, u64d, rd, 1e-3, loss=loss)
+        if it == 0:
+            torch.cuda.synchronize()
+            first = float(loss.cpu()[0])
+    torch.cuda.synchronize()
+    last = float(net.grads(ud, u64d, rd)[0].cpu()[0])
+    print(f"loss {first:.4e} -> {last:.4e}")
+    assert last < 0.1 * first

@@ -96,3 +96,28 @@ def test_parameter_count():
     params = cr.init_params(0)
     n = sum(w.size + b.size for w, b in params)
     assert n == 83201
+
+
+def test_features_of_a_sine_mode_in_closed_form():
+    """D of sin(k pi x_i) is -4 sin^2(k pi h / 2) sin(k pi x_i), and the sum of
+    sin^2(k pi x_i) over the N interior points is (N + 1) / 2, so the scaled
+    feature is -sin(k pi x_i) / sqrt((N + 1) / (2 N))."""
+    n, k = 127, 5
+    x = np.arange(1, n + 1) / (n + 1)
+    u = np.sin(k * np.pi * x)[None, :] * 3.0
+    feat, s = cr.features(u, np.array([2.0]))
+    np.testing.assert_allclose(feat[0, :, 0], -np.sin(k * np.pi * x) / np.sqrt((n + 1) / (2 * n)),
+                               atol=1e-12)
+    h = 1.0 / (n + 1)
+    assert s[0] == pytest.approx(3.0 * 4 * np.sin(k * np.pi * h / 2) ** 2 *
+                                 np.sqrt((n + 1) / (2 * n)), rel=1e-12)
+    np.testing.assert_array_equal(feat[0, :, 1], (2.0 - 1.25) / 0.75)
+
+
+def test_jump_inverts_target():
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((2, 16))
+    u64 = u + 1e-3 * rng.standard_normal((2, 16))
+    r = np.array([0.7, 1.9])
+    _, s = cr.features(u, r)
+    np.testing.assert_allclose(cr.jump(u, cr.target(u, u64, r, s), r, s), u64, rtol=0, atol=1e-15)

@@ -266,6 +266,37 @@ ge_status ge_nn_gradient(ge_nn_t net, float *grad /* device, param_count */, voi
 ge_status ge_nn_train_step(ge_nn_t net, const float *u, const float *u64, const float *r,
                            int32_t batch, float lr, float *loss, void *stream);
 
+/* Surrogate time stepping with a re-check and a fallback to the GE sweep.
+ * Advances `batch` rods of the network's width (zero walls; u: device,
+ * batch x width floats, updated in place) by njumps jumps of 64 levels,
+ * starting at level step0.  The jumps go in windows of `check` jumps (the
+ * last window may be shorter).  The last jump of each window is also taken
+ * by 64 levels of the GE sweep from the same input, with `ge`: an FP64 batch
+ * plan (ge_batch_plan) of exactly these rods -- batch rods of width points,
+ * in order, with the mesh ratios that r (device, batch floats) holds rounded
+ * to FP32 and zero walls -- and its workspace ge_ws.  A rod whose relative
+ * L2 distance ||u_net - u_GE|| / ||u_GE|| exceeds tol (or is not a number)
+ * restarts the window from its state at the window's start and takes the
+ * whole window by the GE sweep (FP64, rounded to FP32 at the end); the
+ * other rods keep the network's result.
+ * Optional outputs: accepted, fallbacks (device int32 per rod: counts of
+ * accepted and rejected windows, incremented), last_err (device double per
+ * rod: the distance at the last check), *n_fallback (host: rejected
+ * rod-windows in this call).  The GE state lives in network-owned buffers;
+ * the stream is synchronised once per window to learn whether any rod was
+ * rejected, and the fallback sweep (whole batch, rejected rods kept) runs
+ * only then.  Errors: GE_ERR_INVALID (arguments, a plan that is not FP64 or
+ * does not match the rods), GE_ERR_HIP. */
+ge_status ge_nn_advance(ge_nn_t net, ge_batch_t ge, void *ge_ws, float *u, const float *r,
+                        int32_t batch, int64_t step0, int32_t njumps, int32_t check,
+                        double tol, int32_t *accepted, int32_t *fallbacks, double *last_err,
+                        int64_t *n_fallback, void *stream);
+
+/* Element-wise precision conversions on the device (n elements, enqueued on
+ * the stream): FP32 to FP64 and FP64 to FP32 (round to nearest). */
+ge_status ge_f32_to_f64(const float *x, double *y, int64_t n, void *stream);
+ge_status ge_f64_to_f32(const double *x, float *y, int64_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -252,11 +252,19 @@ struct ge_batch_s {
     BatchRod *d_rods;
     BatchTask *d_tasks;
     hipStream_t cap;        // private stream used only for capture
-    hipGraphExec_t exec;
-    bool have_exec;
-    void *key_u, *key_ws;
-    int key_parity;
-    int64_t key_nsteps;
+    // instantiated graphs, one per (state, workspace, parity, level count),
+    // the least recently used replaced when all slots are taken
+    struct Graph {
+        hipGraphExec_t exec;
+        void *u, *ws;
+        int parity;
+        int64_t nsteps;
+        uint64_t used;
+    };
+    static constexpr int kGraphs = 4;
+    Graph graphs[kGraphs];
+    int ngraphs;
+    uint64_t clock;
 };
 
 namespace {
@@ -279,7 +287,7 @@ ge_status hip_fail(hipError_t e, const char *what)
 void free_batch(ge_batch_s *b)
 {
     if (!b) return;
-    if (b->have_exec) (void)hipGraphExecDestroy(b->exec);
+    for (int i = 0; i < b->ngraphs; ++i) (void)hipGraphExecDestroy(b->graphs[i].exec);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->d_rods) (void)hipFree(b->d_rods);
     if (b->d_tasks) (void)hipFree(b->d_tasks);
@@ -501,6 +509,19 @@ void ge_batch_destroy(ge_batch_t b) { free_batch(b); }
 
 size_t ge_batch_workspace_bytes(ge_batch_t b) { return b ? 256 : 0; }
 
+}  // extern "C"
+
+bool ge::batch_shape(ge_batch_t b, int64_t *nrods, const int64_t **n, int *prec)
+{
+    if (!b) return false;
+    *nrods = b->nrods;
+    *n = b->n.data();
+    *prec = b->prec;
+    return true;
+}
+
+extern "C" {
+
 int64_t ge_batch_state_elems(ge_batch_t b)
 {
     if (!b) return -1;
@@ -535,12 +556,12 @@ ge_status ge_solve_batch(ge_batch_t b, void *u, void *workspace, int64_t step0, 
         return GE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int parity = (int)(step0 & 1);
-    if (!b->have_exec || b->key_u != u || b->key_ws != workspace || b->key_parity != parity ||
-        b->key_nsteps != nsteps) {
-        if (b->have_exec) {
-            (void)hipGraphExecDestroy(b->exec);
-            b->have_exec = false;
-        }
+    ge_batch_s::Graph *slot = nullptr;
+    for (int i = 0; i < b->ngraphs; ++i) {
+        ge_batch_s::Graph &g = b->graphs[i];
+        if (g.u == u && g.ws == workspace && g.parity == parity && g.nsteps == nsteps) slot = &g;
+    }
+    if (!slot) {
         ge::BatchArgs a{};
         a.u = u;
         a.rods = b->d_rods;
@@ -560,16 +581,24 @@ ge_status ge_solve_batch(ge_batch_t b, void *u, void *workspace, int64_t step0, 
             return hip_fail(le, "ge_solve_batch: capture launch");
         }
         if (e != hipSuccess) return hip_fail(e, "ge_solve_batch: end capture");
-        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return hip_fail(e, "ge_solve_batch: instantiate");
-        b->have_exec = true;
-        b->key_u = u;
-        b->key_ws = workspace;
-        b->key_parity = parity;
-        b->key_nsteps = nsteps;
+        if (b->ngraphs < ge_batch_s::kGraphs) {
+            slot = &b->graphs[b->ngraphs++];
+        } else {
+            slot = &b->graphs[0];
+            for (int i = 1; i < b->ngraphs; ++i)
+                if (b->graphs[i].used < slot->used) slot = &b->graphs[i];
+            // the replaced graph may still be queued on a stream: wait for it
+            (void)hipDeviceSynchronize();
+            (void)hipGraphExecDestroy(slot->exec);
+        }
+        *slot = ge_batch_s::Graph{exec, u, workspace, parity, nsteps, 0};
     }
-    hipError_t e = hipGraphLaunch(b->exec, st);
+    slot->used = ++b->clock;
+    hipError_t e = hipGraphLaunch(slot->exec, st);
     return e == hipSuccess ? GE_OK : hip_fail(e, "ge_solve_batch: graph launch");
 }
 

@@ -23,6 +23,9 @@ SchemeCoef scheme_coef(double r);
 
 int64_t comp_offset(int64_t n);
 
+// Rod count, points per rod and precision of a batch plan; false for NULL.
+bool batch_shape(ge_batch_t b, int64_t *nrods, const int64_t **n, int *prec);
+
 // Message recorded by the last set_error on the calling thread.
 const char *last_error_str();
 

@@ -14,7 +14,7 @@ struct ConvArgs {
     const void *w;        // bf16 [5][cout][cin]
     const float *bias;    // [cout] or null
     int width;            // points per rod, a multiple of 128
-    void *pre_out;        // bf16 [..][cout]  (kEpiGelu*)
+    void *pre_out;        // bf16 [..][cout]  (kEpiGelu*; null: not stored)
     void *act_out;        // bf16 [..][cout]  (kEpiGelu*)
     float *out_f32;       // f32 [batch][width] (kEpiOut)
     const void *res_in;   // bf16 [..][cout]  (kEpiBwd, or null)
@@ -49,6 +49,15 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, 
                        float b1, float b2, float eps, int step, hipStream_t s);
 hipError_t launch_pack(const float *wm, const float *bm, int ci, int co, int cip, int cop,
                        int cod, void *wf, float *bf, void *wd, hipStream_t s);
+
+hipError_t launch_widen(const float *u, double *d, int64_t M, hipStream_t s);
+hipError_t launch_narrow(const double *d, float *u, int64_t M, hipStream_t s);
+hipError_t launch_recheck(const float *a, const double *b, int W, int batch, double tol, int *flag,
+                          double *err, int *acc, int *fb, int *count, hipStream_t s);
+hipError_t launch_select(float *u, const float *unn, const float *save, const int *flag, int W,
+                         int batch, hipStream_t s);
+hipError_t launch_take_ge(float *u, const double *ge, const int *flag, int W, int batch,
+                          hipStream_t s);
 
 }  // namespace nn
 }  // namespace ge

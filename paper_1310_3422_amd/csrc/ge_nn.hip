@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a)
                 if (a.bias) v += a.bias[ch];
                 const int64_t o = (rowbase + w) * COUT + ch;
                 if constexpr (EPI == kEpiGelu || EPI == kEpiGeluRes) {
-                    static_cast<bf16 *>(a.pre_out)[o] = f2bf(v);
+                    if (a.pre_out) static_cast<bf16 *>(a.pre_out)[o] = f2bf(v);
                     float act = gelu(v);
                     if constexpr (EPI == kEpiGeluRes) act += bf2f(xs[(pl + 2) * XS + ch]);
                     static_cast<bf16 *>(a.act_out)[o] = f2bf(act);
@@ -358,6 +358,84 @@ __global__ void jump_kernel(const float *u, const float *out, const float *r,
     u_next[i] = u[i] + 64.0f * r[b] * scale[b] * out[i];
 }
 
+// Widening and narrowing copies between the network's FP32 state and the
+// FP64 state of the GE sweep.
+__global__ void widen_kernel(const float *u, double *d, int64_t M)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) d[i] = (double)u[i];
+}
+__global__ void narrow_kernel(const double *d, float *u, int64_t M)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) u[i] = (float)d[i];
+}
+
+// Re-check of one jump, one workgroup per rod: rel-L2 distance of the
+// network's result a (FP32) from the GE result b (FP64), in FP64.  A rod is
+// flagged when the distance exceeds tol or is not a number; the per-rod
+// counters of accepted and rejected windows are advanced.
+__global__ __launch_bounds__(256) void recheck_kernel(const float *a, const double *b, int W,
+                                                      double tol, int *flag, double *err,
+                                                      int *acc, int *fb)
+{
+    const int rod = blockIdx.x, tid = threadIdx.x;
+    const float *ar = a + (int64_t)rod * W;
+    const double *br = b + (int64_t)rod * W;
+    __shared__ double rd[256], rn[256];
+    double d2 = 0.0, n2 = 0.0;
+    for (int i = tid; i < W; i += 256) {
+        const double d = (double)ar[i] - br[i];
+        d2 += d * d;
+        n2 += br[i] * br[i];
+    }
+    rd[tid] = d2;
+    rn[tid] = n2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            rd[tid] += rd[tid + s];
+            rn[tid] += rn[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double rel = rn[0] > 0.0 ? sqrt(rd[0] / rn[0]) : (rd[0] > 0.0 ? INFINITY : 0.0);
+        const int f = !(rel <= tol);
+        flag[rod] = f;
+        if (err) err[rod] = rel;
+        if (acc) acc[rod] += 1 - f;
+        if (fb) fb[rod] += f;
+    }
+}
+
+// Number of flagged rods, summed in order by one thread.
+__global__ void count_kernel(const int *flag, int n, int *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int c = 0;
+        for (int i = 0; i < n; ++i) c += flag[i];
+        out[0] = c;
+    }
+}
+
+// u = flagged ? saved : network result, rod by rod.
+__global__ void select_kernel(float *u, const float *unn, const float *save, const int *flag,
+                              int W, int64_t M)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    u[i] = flag[i / W] ? save[i] : unn[i];
+}
+
+// Flagged rods take the GE result.
+__global__ void take_ge_kernel(float *u, const double *ge, const int *flag, int W, int64_t M)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    if (flag[i / W]) u[i] = (float)ge[i];
+}
+
 // Adam on the FP32 master parameters.
 __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n, float lr,
                             float b1, float b2, float eps, float c1, float c2)
@@ -488,6 +566,49 @@ hipError_t launch_pack(const float *wm, const float *bm, int ci, int co, int cip
     hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, wm, bm,
                        ci, co, cip, cop, cod, static_cast<bf16 *>(wf), bf,
                        static_cast<bf16 *>(wd));
+    return hipGetLastError();
+}
+
+namespace {
+inline dim3 grid_for(int64_t M) { return dim3((unsigned)((M + 255) / 256)); }
+}  // namespace
+
+hipError_t launch_widen(const float *u, double *d, int64_t M, hipStream_t s)
+{
+    hipLaunchKernelGGL(widen_kernel, grid_for(M), dim3(256), 0, s, u, d, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_narrow(const double *d, float *u, int64_t M, hipStream_t s)
+{
+    hipLaunchKernelGGL(narrow_kernel, grid_for(M), dim3(256), 0, s, d, u, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_recheck(const float *a, const double *b, int W, int batch, double tol, int *flag,
+                          double *err, int *acc, int *fb, int *count, hipStream_t s)
+{
+    hipLaunchKernelGGL(recheck_kernel, dim3(batch), dim3(256), 0, s, a, b, W, tol, flag, err, acc,
+                       fb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_kernel, dim3(1), dim3(64), 0, s, flag, batch, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(float *u, const float *unn, const float *save, const int *flag, int W,
+                         int batch, hipStream_t s)
+{
+    const int64_t M = (int64_t)W * batch;
+    hipLaunchKernelGGL(select_kernel, grid_for(M), dim3(256), 0, s, u, unn, save, flag, W, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_take_ge(float *u, const double *ge, const int *flag, int W, int batch,
+                          hipStream_t s)
+{
+    const int64_t M = (int64_t)W * batch;
+    hipLaunchKernelGGL(take_ge_kernel, grid_for(M), dim3(256), 0, s, u, ge, flag, W, M);
     return hipGetLastError();
 }
 

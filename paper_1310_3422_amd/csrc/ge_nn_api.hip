@@ -87,6 +87,10 @@ struct ge_nn_s {
     float *out, *scale, *loss_part, *wpart;
     void *gl;                       // bf16 [B][W][32] loss gradient
     void *gh, *gp[2];               // bf16 [B][W][64]
+    float *save, *unn;              // re-checked stepping: window start, network result
+    double *gev;                    // re-checked stepping: GE state (FP64)
+    int *flag, *count;              // per-rod rejection flags and their number
+    int *h_count;                   // pinned host copy of the number
     int step;
     std::vector<void *> allocs;
 };
@@ -97,6 +101,7 @@ void free_nn(ge_nn_s *n)
 {
     if (!n) return;
     for (void *p : n->allocs) (void)hipFree(p);
+    if (n->h_count) (void)hipHostFree(n->h_count);
     delete n;
 }
 
@@ -131,7 +136,9 @@ ge_status check_io(ge_nn_s *n, int batch, const char *what)
     return GE_OK;
 }
 
-hipError_t forward(ge_nn_s *n, const float *u, const float *r, int batch, hipStream_t s)
+// train: keep the pre-activations for the backward pass
+hipError_t forward(ge_nn_s *n, const float *u, const float *r, int batch, hipStream_t s,
+                   bool train)
 {
     const int W = n->width;
     hipError_t e = launch_features(u, r, W, batch, n->x, n->scale, s);
@@ -144,7 +151,7 @@ hipError_t forward(ge_nn_s *n, const float *u, const float *r, int batch, hipStr
         a.bias = n->bf[l];
         a.width = W;
         if (l < 5) {
-            a.pre_out = n->pre[l];
+            a.pre_out = train ? n->pre[l] : nullptr;
             a.act_out = n->h[l];
         } else {
             a.out_f32 = n->out;
@@ -242,6 +249,10 @@ ge_status ge_nn_create(ge_nn_t *out, int32_t width, int32_t max_batch, uint64_t 
               dalloc(n, &n->gp[0], M * 64 * 2) && dalloc(n, &n->gp[1], M * 64 * 2);
     for (int l = 0; ok && l < 5; ++l)
         ok = dalloc(n, &n->pre[l], M * 64 * 2) && dalloc(n, &n->h[l], M * 64 * 2);
+    ok = ok && dalloc(n, &n->save, M * 4) && dalloc(n, &n->unn, M * 4) &&
+         dalloc(n, &n->gev, M * 8) && dalloc(n, &n->flag, (size_t)max_batch * 4) &&
+         dalloc(n, &n->count, 256);
+    ok = ok && hipHostMalloc((void **)&n->h_count, sizeof(int), hipHostMallocDefault) == hipSuccess;
     for (int l = 0; ok && l < 6; ++l) {
         const Layer &L = kLayers[l];
         ok = dalloc(n, &n->wf[l], 5LL * L.cop * L.cip * 2) && dalloc(n, &n->bf[l], L.cop * 4);
@@ -309,7 +320,7 @@ ge_status ge_nn_forward(ge_nn_t n, const float *u, const float *r, int32_t batch
     if (st != GE_OK) return st;
     if (!u || !r) return fail(GE_ERR_INVALID, "ge_nn_forward: u and r must be given");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = forward(n, u, r, batch, s);
+    hipError_t e = forward(n, u, r, batch, s, false);
     const size_t M = (size_t)batch * n->width;
     if (e == hipSuccess && out) e = hipMemcpyAsync(out, n->out, M * 4, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && scale)
@@ -324,7 +335,7 @@ ge_status ge_nn_jump(ge_nn_t n, const float *u, const float *r, int32_t batch, f
     if (st != GE_OK) return st;
     if (!u || !r || !u_next) return fail(GE_ERR_INVALID, "ge_nn_jump: NULL argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = forward(n, u, r, batch, s);
+    hipError_t e = forward(n, u, r, batch, s, false);
     if (e == hipSuccess) e = launch_jump(u, n->out, r, n->scale, n->width, batch, u_next, s);
     return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_jump: %s", hipGetErrorString(e));
 }
@@ -336,7 +347,7 @@ ge_status ge_nn_grads(ge_nn_t n, const float *u, const float *u64, const float *
     if (st != GE_OK) return st;
     if (!u || !u64 || !r) return fail(GE_ERR_INVALID, "ge_nn_grads: NULL argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = forward(n, u, r, batch, s);
+    hipError_t e = forward(n, u, r, batch, s, true);
     if (e == hipSuccess)
         e = launch_loss(n->out, u, u64, r, n->scale, n->width, batch, n->gl, n->loss_part, loss, s);
     if (e == hipSuccess) e = backward(n, batch, s);
@@ -364,6 +375,80 @@ ge_status ge_nn_train_step(ge_nn_t n, const float *u, const float *u64, const fl
                                n->step, s);
     if (e == hipSuccess) e = pack_all(n, s);
     return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_train_step: %s", hipGetErrorString(e));
+}
+
+ge_status ge_f32_to_f64(const float *x, double *y, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(GE_ERR_INVALID, "ge_f32_to_f64: bad arguments");
+    if (n == 0) return GE_OK;
+    hipError_t e = launch_widen(x, y, n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_f32_to_f64: %s", hipGetErrorString(e));
+}
+
+ge_status ge_f64_to_f32(const double *x, float *y, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(GE_ERR_INVALID, "ge_f64_to_f32: bad arguments");
+    if (n == 0) return GE_OK;
+    hipError_t e = launch_narrow(x, y, n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_f64_to_f32: %s", hipGetErrorString(e));
+}
+
+ge_status ge_nn_advance(ge_nn_t n, ge_batch_t ge, void *ge_ws, float *u, const float *r,
+                        int32_t batch, int64_t step0, int32_t njumps, int32_t check, double tol,
+                        int32_t *accepted, int32_t *fallbacks, double *last_err,
+                        int64_t *n_fallback, void *stream)
+{
+    ge_status st = check_io(n, batch, "ge_nn_advance");
+    if (st != GE_OK) return st;
+    if (!u || !r || !ge || !ge_ws) return fail(GE_ERR_INVALID, "ge_nn_advance: NULL argument");
+    if (njumps < 0 || check < 1 || step0 < 0 || !(tol >= 0.0))
+        return fail(GE_ERR_INVALID, "ge_nn_advance: need njumps >= 0, check >= 1, step0 >= 0, tol >= 0");
+    int64_t nrods = 0;
+    const int64_t *rod_n = nullptr;
+    int prec = -1;
+    ge::batch_shape(ge, &nrods, &rod_n, &prec);
+    if (nrods != batch || prec != GE_FP64)
+        return fail(GE_ERR_INVALID, "ge_nn_advance: the GE plan must be FP64 with %d rods", batch);
+    for (int64_t i = 0; i < nrods; ++i)
+        if (rod_n[i] != n->width)
+            return fail(GE_ERR_INVALID, "ge_nn_advance: GE rod %lld has %lld points, need %d",
+                        (long long)i, (long long)rod_n[i], n->width);
+    if (n_fallback) *n_fallback = 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int W = n->width;
+    const int64_t M = (int64_t)W * batch;
+    hipError_t e = hipSuccess;
+    for (int32_t j0 = 0; j0 < njumps && e == hipSuccess; j0 += check) {
+        const int nj = std::min(check, njumps - j0);
+        const int64_t lev0 = step0 + 64LL * j0;
+        e = hipMemcpyAsync(n->save, u, M * 4, hipMemcpyDeviceToDevice, s);
+        for (int j = 0; j + 1 < nj && e == hipSuccess; ++j) {
+            e = forward(n, u, r, batch, s, false);
+            if (e == hipSuccess) e = launch_jump(u, n->out, r, n->scale, W, batch, u, s);
+        }
+        // the window's last jump, by the network and by 64 GE levels
+        if (e == hipSuccess) e = forward(n, u, r, batch, s, false);
+        if (e == hipSuccess) e = launch_jump(u, n->out, r, n->scale, W, batch, n->unn, s);
+        if (e == hipSuccess) e = launch_widen(u, n->gev, M, s);
+        if (e != hipSuccess) break;
+        st = ge_solve_batch(ge, n->gev, ge_ws, lev0 + 64LL * (nj - 1), 64, s);
+        if (st != GE_OK) return st;
+        e = launch_recheck(n->unn, n->gev, W, batch, tol, n->flag, last_err, accepted, fallbacks,
+                           n->count, s);
+        if (e == hipSuccess) e = launch_select(u, n->unn, n->save, n->flag, W, batch, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(n->h_count, n->count, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess || *n->h_count == 0) continue;
+        // rejected rods restart the window from its first state and take it by GE
+        if (n_fallback) *n_fallback += *n->h_count;
+        e = launch_widen(u, n->gev, M, s);
+        if (e != hipSuccess) break;
+        st = ge_solve_batch(ge, n->gev, ge_ws, lev0, 64LL * nj, s);
+        if (st != GE_OK) return st;
+        e = launch_take_ge(u, n->gev, n->flag, W, batch, s);
+    }
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_advance: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

@@ -74,6 +74,10 @@ _SIGS = {
     "ge_nn_grads": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp]),
     "ge_nn_gradient": (ctypes.c_int, [_vp, _vp, _vp]),
     "ge_nn_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, _vp, _vp]),
+    "ge_nn_advance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i32, _i32, _dbl,
+                                     _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
+    "ge_f32_to_f64": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
+    "ge_f64_to_f32": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
 }
 
 
@@ -397,9 +401,40 @@ class Net:
         check(lib().ge_nn_gradient(self.handle, _ptr(g), _stream_ptr(stream)))
         return loss, g
 
+    def advance(self, ge_batch, ge_ws, u, r, njumps, step0=0, check=8, tol=1e-4,
+                accepted=None, fallbacks=None, last_err=None, stream=None):
+        """Re-checked surrogate stepping (ge_nn_advance); returns the number
+        of rod-windows that fell back to the GE sweep."""
+        b = r.numel()
+        self._check(u, b * self.width, "u")
+        self._check(r, b, "r")
+        nfb = _i64(0)
+        check_status = lib().ge_nn_advance(
+            self.handle, ge_batch.handle, _ptr(ge_ws), _ptr(u), _ptr(r), b, int(step0),
+            int(njumps), int(check), float(tol), _ptr(accepted), _ptr(fallbacks),
+            _ptr(last_err), ctypes.byref(nfb), _stream_ptr(stream))
+        check(check_status)
+        return int(nfb.value)
+
     def train_step(self, u, u64, r, lr, loss=None, stream=None):
         b = r.numel()
         for t, name in ((u, "u"), (u64, "u64")):
             self._check(t, b * self.width, name)
         check(lib().ge_nn_train_step(self.handle, _ptr(u), _ptr(u64), _ptr(r), b, float(lr),
                                      _ptr(loss), _stream_ptr(stream)))
+
+
+def f32_to_f64(x, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(x.numel(), dtype=torch.float64, device=x.device)
+    check(lib().ge_f32_to_f64(_ptr(x), _ptr(out), x.numel(), _stream_ptr(stream)))
+    return out
+
+
+def f64_to_f32(x, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(x.numel(), dtype=torch.float32, device=x.device)
+    check(lib().ge_f64_to_f32(_ptr(x), _ptr(out), x.numel(), _stream_ptr(stream)))
+    return out

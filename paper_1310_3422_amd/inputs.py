@@ -112,7 +112,8 @@ def moving_wall_rod(n, r=4.0, nsteps=5000, step0=0):
 
 def surrogate_rods(seed, nrods, n=4096, rmin=0.5, rmax=2.0):
     """Initial values and mesh ratios for surrogate training/evaluation:
-    draws r (nrods) then z (nrods x 16); zero walls."""
+    draws r (nrods) then z (nrods x 16); zero walls.  ``seed`` may be an int
+    or a sequence of ints (a data set split into seeded chunks)."""
     rng = np.random.default_rng(seed)
     r = rng.uniform(rmin, rmax, nrods)
     z = rng.standard_normal((nrods, NMODES))

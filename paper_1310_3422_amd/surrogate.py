@@ -1,0 +1,158 @@
+"""Training and use of the learned 64-level propagator (the surrogate).
+
+The network and its training step run in the library (ge_nn_*); this module
+generates the training data with the batch GE sweep, drives the optimiser,
+measures the surrogate against the sweep, and runs re-checked stepping
+(ge_nn_advance).  Data: rods of ``width`` points with zero walls, 16 sine
+modes with coefficients z_k / k^2 (z standard normal) and mesh ratios drawn
+uniformly from [0.5, 2]; a trajectory is the FP64 GE sweep from such a rod,
+sampled every 64 levels.
+"""
+import time
+
+import numpy as np
+
+from . import ge, inputs
+
+JUMP = 64
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def fp64_batch(r, width):
+    """FP64 batch plan for len(r) rods of ``width`` points, zero walls."""
+    nr = len(r)
+    n = np.full(nr, width, dtype=np.int64)
+    offsets = np.arange(nr + 1, dtype=np.int64) * width
+    z = np.zeros(nr)
+    return ge.Batch(n, offsets, np.asarray(r, dtype=np.float64), z, z, precision="fp64")
+
+
+class Trajectories:
+    """Seeded GE trajectories of ``nrods`` rods, with the FP32-rounded state
+    after every 64 levels: states[j] holds level 64 j (j = 0..njumps) of all
+    rods, back to back."""
+
+    def __init__(self, seed, nrods, width=4096, njumps=8, rmin=0.5, rmax=2.0):
+        torch = _torch()
+        r, u0 = inputs.surrogate_rods(seed, nrods, n=width, rmin=rmin, rmax=rmax)
+        self.nrods, self.width, self.njumps = nrods, width, njumps
+        self.r64 = r
+        self.r = torch.from_numpy(r.astype(np.float32)).cuda()
+        self.plan = fp64_batch(r, width)
+        ws = self.plan.new_workspace()
+        state = torch.from_numpy(np.ascontiguousarray(u0).ravel()).cuda()
+        self.states = torch.empty((njumps + 1, nrods * width), dtype=torch.float32, device="cuda")
+        for j in range(njumps + 1):
+            ge.f64_to_f32(state, out=self.states[j])
+            if j < njumps:
+                self.plan.solve(state, JUMP * j, JUMP, ws)
+        self.final64 = state            # FP64 state at level 64 njumps
+
+    def rods(self, j):
+        return self.states[j].view(self.nrods, self.width)
+
+
+class Trainer:
+    """Adam on minibatches of (u, u after 64 levels) pairs drawn from
+    trajectory chunks; chunk c of a data set with seed s uses seed [s, c]."""
+
+    def __init__(self, net, seed=4, ntraj=2048, chunk=1024, njumps=8, minibatch=64):
+        self.net = net
+        self.seed, self.ntraj, self.chunk = seed, ntraj, min(chunk, ntraj)
+        self.njumps, self.minibatch = njumps, minibatch
+        self.rng = np.random.default_rng([seed, 1 << 20])
+        self.chunks = []
+        for c in range((ntraj + self.chunk - 1) // self.chunk):
+            nr = min(self.chunk, ntraj - c * self.chunk)
+            self.chunks.append(Trajectories([seed, c], nr, net.width, njumps))
+        torch = _torch()
+        B, W = minibatch, net.width
+        self.u = torch.empty(B * W, dtype=torch.float32, device="cuda")
+        self.u64 = torch.empty_like(self.u)
+        self.r = torch.empty(B, dtype=torch.float32, device="cuda")
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        self.steps = 0
+
+    def _gather(self):
+        torch = _torch()
+        c = self.chunks[int(self.rng.integers(len(self.chunks)))]
+        rods = torch.from_numpy(self.rng.integers(0, c.nrods, self.minibatch)).cuda()
+        js = torch.from_numpy(self.rng.integers(0, c.njumps, self.minibatch)).cuda()
+        W = self.net.width
+        st = c.states.view(c.njumps + 1, c.nrods, W)
+        self.u.view(-1, W).copy_(st[js, rods])
+        self.u64.view(-1, W).copy_(st[js + 1, rods])
+        self.r.copy_(c.r[rods])
+
+    def train(self, steps, lr=1e-3, lr_final=None, log_every=0):
+        """``steps`` Adam steps with the rate decaying geometrically from lr to
+        lr_final; returns the losses at the logged steps."""
+        lr_final = lr if lr_final is None else lr_final
+        out = []
+        for i in range(steps):
+            rate = lr * (lr_final / lr) ** (i / max(steps - 1, 1))
+            self._gather()
+            self.net.train_step(self.u, self.u64, self.r, rate, loss=self.loss)
+            self.steps += 1
+            if log_every and (i % log_every == 0 or i == steps - 1):
+                out.append((self.steps, float(self.loss.cpu()[0])))
+        return out
+
+
+def rel_l2_rows(x, y):
+    """Per-row ||x - y|| / ||y|| of two (rods, width) arrays, in FP64."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    return np.linalg.norm(x - y, axis=1) / np.maximum(np.linalg.norm(y, axis=1), 1e-300)
+
+
+def evaluate(net, seed=41, nrods=256, width=None, start_jump=1):
+    """Distances of one 64-level jump from the FP64 GE sweep, per rod, for the
+    identity map, one GE level at mesh ratio 64 r (the big step), and the
+    network; each as the state and as the increment.  The jump starts at
+    level 64 start_jump of a fresh trajectory."""
+    torch = _torch()
+    width = width or net.width
+    tr = Trajectories(seed, nrods, width, njumps=start_jump + 1)
+    u = tr.rods(start_jump).contiguous()
+    ref = tr.final64.view(nrods, width).cpu().numpy()
+    u_np = u.cpu().numpy().astype(np.float64)
+    big = fp64_batch(64.0 * tr.r64, width)
+    ub = ge.f32_to_f64(u.view(-1))
+    big.solve(ub, JUMP * start_jump, 1, big.new_workspace())
+    un = torch.empty_like(u.view(-1))
+    for i in range(0, nrods, net.max_batch):
+        b = min(net.max_batch, nrods - i)
+        net.jump(u[i:i + b].reshape(-1), tr.r[i:i + b].contiguous(),
+                 out=un[i * width:(i + b) * width])
+    torch.cuda.synchronize()
+    maps = {"identity": u_np, "big_step": ub.view(nrods, width).cpu().numpy(),
+            "surrogate": un.view(nrods, width).cpu().numpy().astype(np.float64)}
+    res = {}
+    for k, v in maps.items():
+        res[k] = {"rel_l2": rel_l2_rows(v, ref),
+                  "inc_rel_l2": rel_l2_rows(v - u_np, ref - u_np)}
+    return res
+
+
+def advance_with_recheck(net, u, r, njumps, ge_batch=None, r64=None, check=8, tol=1e-4,
+                         step0=0, stream=None):
+    """Re-checked stepping of FP32 rods u (device, batch x width) with mesh
+    ratios r (device FP32); the FP64 GE plan is built from r64 (host) when not
+    given.  Returns (fallback rod-windows, accepted per rod, fallbacks per rod,
+    last distance per rod)."""
+    torch = _torch()
+    b = r.numel()
+    if ge_batch is None:
+        ge_batch = fp64_batch(r64, net.width)
+    ws = ge_batch.new_workspace()
+    acc = torch.zeros(b, dtype=torch.int32, device="cuda")
+    fb = torch.zeros(b, dtype=torch.int32, device="cuda")
+    err = torch.zeros(b, dtype=torch.float64, device="cuda")
+    nfb = net.advance(ge_batch, ws, u, r, njumps, step0=step0, check=check, tol=tol,
+                      accepted=acc, fallbacks=fb, last_err=err, stream=stream)
+    return nfb, acc.cpu().numpy(), fb.cpu().numpy(), err.cpu().numpy()

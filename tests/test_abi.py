@@ -226,3 +226,15 @@ def test_nn_calls_reject_null_network():
     assert lib.ge_nn_get_params(None, None, 0) == ge.GE_ERR_INVALID
     assert lib.ge_nn_gradient(None, None, None) == ge.GE_ERR_INVALID
     lib.ge_nn_destroy(None)
+
+
+def test_advance_and_conversions_validate_before_enqueueing():
+    lib = ge.lib()
+    fake = ctypes.c_void_p(0x1000)
+    n = ctypes.c_int64(7)
+    assert lib.ge_nn_advance(None, fake, fake, fake, fake, 1, 0, 1, 8, 1e-4, None, None, None,
+                             ctypes.byref(n), None) == ge.GE_ERR_INVALID
+    assert lib.ge_f32_to_f64(fake, fake, -1, None) == ge.GE_ERR_INVALID
+    assert lib.ge_f64_to_f32(None, None, 5, None) == ge.GE_ERR_INVALID
+    assert lib.ge_f32_to_f64(None, None, 0, None) == ge.GE_OK
+    assert lib.ge_f64_to_f32(None, None, 0, None) == ge.GE_OK

@@ -76,6 +76,46 @@ __device__ __forceinline__ double from_right(double fill, double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// The same shifts where the lane without a source may receive any value (a
+// wave whose edges are open window edges: those points lie in the halo).
+// bound_ctrl makes that lane read zero, so no fill operand has to be set up.
+__device__ __forceinline__ int shr1z_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int shl1z_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ float from_left_open(float v)
+{
+    return __int_as_float(shr1z_i(__float_as_int(v)));
+}
+__device__ __forceinline__ float from_right_open(float v)
+{
+    return __int_as_float(shl1z_i(__float_as_int(v)));
+}
+__device__ __forceinline__ double from_left_open(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = shr1z_i((int)(b & 0xffffffffll)), hi = shr1z_i((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_right_open(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = shl1z_i((int)(b & 0xffffffffll)), hi = shl1z_i((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// edge value from the left / right neighbour lane, with the fill used only
+// when the wave's edge is not open
+template <bool OPEN, typename T>
+__device__ __forceinline__ T edge_left(T fill, T v)
+{
+    if constexpr (OPEN) return from_left_open(v);
+    else return from_left(fill, v);
+}
+template <bool OPEN, typename T>
+__device__ __forceinline__ T edge_right(T fill, T v)
+{
+    if constexpr (OPEN) return from_right_open(v);
+    else return from_right(fill, v);
+}
+
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -294,8 +334,9 @@ struct FluxTap {
 //          fill from the neighbouring waves, a wall value, or anything at
 //          an open window edge); yl.. the same for e
 // WALL instantiations apply the lone-point formulas and the flux tap; every
-// other point of every instantiation evaluates the same expressions.
-template <typename T, int K, bool COMP, bool SRC, bool WALL, int P>
+// other point of every instantiation evaluates the same expressions.  OPEN:
+// both edges of the wave are open window edges, so the fills are not used.
+template <typename T, int K, bool COMP, bool SRC, bool WALL, int P, bool OPEN = false>
 __device__ __forceinline__ void ge_level(T (&s)[K], T (&e)[K], const T (&b)[K], T bl, T br,
                                          T xl, T xl2, T xr, T xr2, T yl, T yl2, T yr, T yr2,
                                          const Coef<T> &c, T an,
@@ -303,9 +344,9 @@ __device__ __forceinline__ void ge_level(T (&s)[K], T (&e)[K], const T (&b)[K], 
 {
     const T c1 = c.c1, c2 = c.c2, cs = c.cs, e1 = c.e1, e2 = c.e2, es = c.es;
     // u_{-1} and u_K: neighbour lanes' edge points
-    const T sl = from_left(xl, s[K - 1]), sr = from_right(xr, s[0]);
+    const T sl = edge_left<OPEN>(xl, s[K - 1]), sr = edge_right<OPEN>(xr, s[0]);
     T el = T(0), er = T(0);
-    if constexpr (COMP) { el = from_left(yl, e[K - 1]); er = from_right(yr, e[0]); }
+    if constexpr (COMP) { el = edge_left<OPEN>(yl, e[K - 1]); er = edge_right<OPEN>(yr, e[0]); }
 
     auto dif = [](T s1, T e1_, T s0, T e0) { return ::ge::dev::dif<T, COMP>(s1, e1_, s0, e0); };
     auto sd = [](Dif<T, COMP> da, Dif<T, COMP> db) { return ::ge::dev::sd<T, COMP>(da, db); };
@@ -379,9 +420,12 @@ __device__ __forceinline__ void ge_level(T (&s)[K], T (&e)[K], const T (&b)[K], 
         // pairs (-1,0), (1,2), ..., (K-1,K): the lane's edge points pair
         // with the neighbouring lanes' edge points, so u_{-2} and u_{K+1}
         // are needed too
-        const T sl2 = from_left(xl2, s[K - 2]), sr2 = from_right(xr2, s[1]);
+        const T sl2 = edge_left<OPEN>(xl2, s[K - 2]), sr2 = edge_right<OPEN>(xr2, s[1]);
         T el2 = T(0), er2 = T(0);
-        if constexpr (COMP) { el2 = from_left(yl2, e[K - 2]); er2 = from_right(yr2, e[1]); }
+        if constexpr (COMP) {
+            el2 = edge_left<OPEN>(yl2, e[K - 2]);
+            er2 = edge_right<OPEN>(yr2, e[1]);
+        }
         const auto dm2 = dif(sl, el, sl2, el2);                     // d_{-2}
         const auto dm1 = dif(s[0], e[0], sl, el);                   // d_{-1}
         const auto d0 = dif(s[1], e[1], s[0], e[0]);                // d_0

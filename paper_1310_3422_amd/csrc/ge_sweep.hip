@@ -153,8 +153,8 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
         Lone<T> lone{T(0), T(0)};
         if (WALL && singR)
             lone = right_lone<T, K, COMP, SRC>(s, e, b, kS, xl, yl, gr_hi, gr_lo, dgr, cf, an);
-        ge_level<T, K, COMP, SRC, WALL, p>(s, e, b, bl, br, xl, xl2, xr, xr2, yl, yl2, yr,
-                                           yr2, cf, an, wlv, ft);
+        ge_level<T, K, COMP, SRC, WALL, p, NW == 1 && !WALL>(s, e, b, bl, br, xl, xl2, xr, xr2,
+                                                             yl, yl2, yr, yr2, cf, an, wlv, ft);
         if (WALL && singR) {
             put_at<T, K>(s, kS, tid == lS, lone.s);
             if constexpr (COMP) put_at<T, K>(e, kS, tid == lS, lone.e);
@@ -252,7 +252,7 @@ bool tile_config_supported(int prec, int k, int nw)
     if (nw != 1 && nw != 4)
         return false;
     switch (prec) {
-    case kFP64: return k == 2 || k == 4 || k == 8 || k == 16;
+    case kFP64: return k == 2 || k == 4 || k == 8 || k == 16 || k == 32;
     case kFP32: return k == 4 || k == 8 || k == 16 || k == 32;
     case kFP32C: return k == 4 || k == 8 || k == 16;
     default: return false;
@@ -268,6 +268,7 @@ hipError_t launch_tiles(int prec, int k, int nw, bool src, const TileArgs &a,
         if (k == 4) return launch_nw<double, 4, false>(nw, src, a, stream);
         if (k == 8) return launch_nw<double, 8, false>(nw, src, a, stream);
         if (k == 16) return launch_nw<double, 16, false>(nw, src, a, stream);
+        if (k == 32) return launch_nw<double, 32, false>(nw, src, a, stream);
         break;
     case kFP32:
         if (k == 4) return launch_nw<float, 4, false>(nw, src, a, stream);

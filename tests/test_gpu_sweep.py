@@ -86,7 +86,8 @@ def test_max_norm_never_grows_at_r_one():
 # ------------------------------------------------------- multi-tile ------
 CONFIGS_FP64 = [dict(tile=8, waves=1, depth=1), dict(tile=8, waves=1, depth=8),
                 dict(tile=16, waves=1, depth=13), dict(tile=16, waves=4, depth=32),
-                dict(tile=8, waves=4, depth=64)]
+                dict(tile=8, waves=4, depth=64), dict(tile=32, waves=1, depth=48),
+                dict(tile=32, waves=4, depth=96)]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS_FP64, ids=lambda c: f"k{c['tile']}w{c['waves']}d{c['depth']}")
@@ -129,7 +130,7 @@ def test_bitwise_invariance_across_tiling_depth_and_calls(precision):
     n, s = 30011, 40
     rng = np.random.default_rng(17)
     u0 = inputs.sine_rod(n, 17) + 0.05 * rng.standard_normal(n)
-    tiles = {"fp64": (2, 4, 8, 16), "fp32": (4, 8, 16, 32), "fp32c": (4, 8, 16)}[precision]
+    tiles = {"fp64": (2, 4, 8, 16, 32), "fp32": (4, 8, 16, 32), "fp32c": (4, 8, 16)}[precision]
     results = []
     for tile in tiles:
         for waves in (1, 4):

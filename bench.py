@@ -116,6 +116,82 @@ def cpu_baseline(u0, target_s):
                       f"{threads} threads with a barrier per level, {dt:.1f} s"}
 
 
+def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
+    """The learned 64-level propagator against the plain GE sweep on a batch
+    of rods: its training (data from the FP64 batch sweep), its distance from
+    64 GE levels, and the time per rod-jump of each way to advance 64 levels
+    (identity, one GE level at 64 r, 64 GE levels in FP64 and FP32, the
+    network, and re-checked stepping at tol 1e-4 every 8 jumps)."""
+    from paper_1310_3422_amd import ge, surrogate, inputs
+    t0 = time.perf_counter()
+    net = ge.Net(width=width, max_batch=nrods, seed=4)
+    tr = surrogate.Trainer(net, seed=4, ntraj=4096, chunk=1024, njumps=8, minibatch=64)
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    log = tr.train(train_steps, lr=2e-3, lr_final=5e-5, log_every=max(train_steps // 8, 1))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    res = surrogate.evaluate(net, seed=41, nrods=512, width=width)
+    med = {k: {m: float(np.median(v[m])) for m in v} for k, v in res.items()}
+    # timing at a batch of nrods rods
+    r, u0 = inputs.surrogate_rods(42, nrods, n=width)
+    rf = torch.from_numpy(r.astype(np.float32)).cuda()
+    u32 = torch.from_numpy(u0.astype(np.float32).ravel()).cuda()
+    r64 = r.astype(np.float32).astype(np.float64)
+    out = {"train_steps": train_steps, "train_minibatch": 64, "trajectories": 4096,
+           "data_gen_s": round(gen_s, 2), "train_s": round(train_s, 2),
+           "loss_log": log, "median_rel_l2_vs_ge64": med, "batch_rods": nrods,
+           "width": width}
+    times = {}
+    plan64 = surrogate.fp64_batch(r64, width)
+    ws64 = plan64.new_workspace()
+    u64 = ge.f32_to_f64(u32)
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        _, g = time_runs(torch, stream, lambda: plan64.solve(u64, 0, 64, ws64, stream=stream), 1, 5)
+    times["ge64_fp64"] = g / 5
+    n = np.full(nrods, width, dtype=np.int64)
+    offs = np.arange(nrods + 1, dtype=np.int64) * width
+    plan32 = ge.Batch(n, offs, r64, np.zeros(nrods), np.zeros(nrods), precision="fp32")
+    ws32 = plan32.new_workspace()
+    u32b = u32.clone()
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        _, g = time_runs(torch, stream, lambda: plan32.solve(u32b, 0, 64, ws32, stream=stream), 1, 5)
+    times["ge64_fp32"] = g / 5
+    big = surrogate.fp64_batch(64.0 * r64, width)
+    wsb = big.new_workspace()
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        _, g = time_runs(torch, stream, lambda: big.solve(u64, 0, 1, wsb, stream=stream), 1, 5)
+    times["big_step_fp64"] = g / 5
+    un = torch.empty_like(u32)
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        _, g = time_runs(torch, stream, lambda: net.jump(u32, rf, out=un, stream=stream), 1, 5)
+    times["surrogate_jump"] = g / 5
+    del un, u32b, u64
+    ua = u32.clone()
+    acc = torch.zeros(nrods, dtype=torch.int32, device="cuda")
+    fb = torch.zeros_like(acc)
+    err = torch.zeros(nrods, dtype=torch.float64, device="cuda")
+    njumps = 16
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nfb = net.advance(plan64, ws64, ua, rf, njumps, check=8, tol=1e-4, accepted=acc,
+                          fallbacks=fb, last_err=err, stream=stream)
+        torch.cuda.synchronize()
+        adv_s = time.perf_counter() - t0
+    times["recheck_advance"] = adv_s / njumps
+    out["recheck"] = {"jumps": njumps, "check_every": 8, "tol": 1e-4,
+                      "rod_windows": nrods * njumps // 8, "fallback_rod_windows": nfb,
+                      "median_last_rel_l2": float(err.median().cpu())}
+    out["us_per_rod_jump"] = {k: round(v / nrods * 1e6, 4) for k, v in times.items()}
+    out["speedup_vs_ge64_fp64"] = {k: round(times["ge64_fp64"] / v, 3) for k, v in times.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,8 +201,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
+    ap.add_argument("--surrogate-steps", type=int, default=3000,
+                    help="training steps of the surrogate extra (0: skip it)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 1 GiB device copy (counter calibration)")
+                    help="first run a 1 GiB fill and a 1 GiB streaming read+write (counter "
+                         "calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -143,9 +222,11 @@ def main():
     n = N_DEFAULT
     prec = args.precision
     if args.calibrate_copy:
+        # counter calibration: a fill that writes 1 GiB, then a streaming
+        # kernel that reads 1 GiB and writes 1 GiB (b = 2 a)
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
     print(f"[bench] generating rod N={n} ...", file=sys.stderr, flush=True)
@@ -269,6 +350,9 @@ def main():
             "ms_per_run": gb / 3 * 1e3, "tasks": info["ntasks"], "workgroups": info["grid"],
             "rods": rb.nrods, "points": int(rb.n.sum()), "levels": 2000}
         del ub, wsb, bt
+        if args.surrogate_steps > 0:
+            print("[bench] surrogate ...", file=sys.stderr, flush=True)
+            extra["surrogate"] = surrogate_extra(torch, stream, args.surrogate_steps)
         out["extra"] = extra
 
     if not args.no_cpu:

@@ -110,6 +110,9 @@ def check(status):
         raise GEError(status, last_error())
 
 
+_check_status = check
+
+
 def comp_offset(n):
     return int(lib().ge_comp_offset(n))
 
@@ -409,11 +412,10 @@ class Net:
         self._check(u, b * self.width, "u")
         self._check(r, b, "r")
         nfb = _i64(0)
-        check_status = lib().ge_nn_advance(
+        _check_status(lib().ge_nn_advance(
             self.handle, ge_batch.handle, _ptr(ge_ws), _ptr(u), _ptr(r), b, int(step0),
             int(njumps), int(check), float(tol), _ptr(accepted), _ptr(fallbacks),
-            _ptr(last_err), ctypes.byref(nfb), _stream_ptr(stream))
-        check(check_status)
+            _ptr(last_err), ctypes.byref(nfb), _stream_ptr(stream)))
         return int(nfb.value)
 
     def train_step(self, u, u64, r, lr, loss=None, stream=None):

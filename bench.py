@@ -308,20 +308,23 @@ def main():
         extra["parity_sample_increment_rel_l2"] = float(
             np.linalg.norm((got - v0[lo:lo + 64]) - (want - v0[lo:lo + 64])) /
             np.linalg.norm(want - v0[lo:lo + 64]))
-        # depth-1 streaming sweep: every level reads and writes the whole rod
-        p1 = ge.Plan(n, R, prec, depth=1)
-        u1 = u_init.clone()
+        # depth-1 streaming sweep on a rod of 2^27 points (1 GiB in FP64, far
+        # beyond the last-level cache): every level reads and writes the rod
+        n5 = 1 << 27
+        p1 = ge.Plan(n5, 4.0, prec, depth=1)
+        u1 = ge.pack_state(inputs.sine_pulse(n5), prec)
         ws1 = p1.new_workspace()
-        lv = 200
+        lv = 20
         with torch.cuda.stream(stream):
             torch.cuda.synchronize()
             w1, g1 = time_runs(torch, stream,
                                lambda: p1.step_n(u1, 0, lv, workspace=ws1, stream=stream), 1, 3)
-        bps = 2 * BYTES_PER_POINT[prec] * n * lv * 3 / g1 / 1e9
-        extra["streaming_depth1"] = {"updates_per_s": n * lv * 3 / w1,
+        bps = 2 * BYTES_PER_POINT[prec] * n5 * lv * 3 / g1 / 1e9
+        extra["streaming_depth1"] = {"n": n5, "levels": lv * 3, "updates_per_s": n5 * lv * 3 / w1,
                                      "hbm_gbs_algorithmic": round(bps, 1),
-                                     "hbm_frac": round(bps / HBM_PEAK_GBS, 4)}
-        del u1, ws1
+                                     "hbm_frac": round(bps / HBM_PEAK_GBS, 4),
+                                     "config": p1.config()}
+        del u1, ws1, p1
         if prec == "fp64":
             pc = ge.Plan(n, R, "fp32c")
             uc = ge.pack_state(u0, "fp32c")

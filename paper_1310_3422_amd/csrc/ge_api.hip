@@ -147,12 +147,19 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
 
     const int prec = d->precision;
     int tile = d->tile, waves = d->waves, depth = d->depth;
-    // Defaults measured on MI355X for long rods (16 points per lane, one
-    // wave per workgroup, 48 levels per launch was the fastest choice for all
-    // three precisions on n = 2^24).
+    // Defaults measured on MI355X on a rod of 2^24 points: FP64 runs best
+    // with 16 points per lane, one wave per workgroup and 48 levels per
+    // launch; both FP32 forms with four waves (4096-point windows) and 128
+    // levels.  A depth left at 0 is clipped so that the halo stays within a
+    // quarter of the window.
+    const bool wide = prec != ge::kFP64;
     if (tile == 0) tile = 16;
-    if (waves == 0) waves = 1;
-    if (depth == 0) depth = 48;
+    if (waves == 0) waves = wide ? 4 : 1;
+    if (depth == 0) {
+        depth = wide ? 128 : 48;
+        const int al = (prec == ge::kFP64) ? 2 : 4;
+        while (depth > 1 && 4 * round_up(depth + 1, al) > (int64_t)waves * 64 * tile) --depth;
+    }
     if (depth < 1)
         return fail(GE_ERR_INVALID, "ge_plan: depth = %d, need depth >= 1", depth);
     if (!ge::tile_config_supported(prec, tile, waves))

@@ -50,6 +50,19 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, 
 hipError_t launch_pack(const float *wm, const float *bm, int ci, int co, int cip, int cop,
                        int cod, void *wf, float *bf, void *wd, hipStream_t s);
 
+// Six-layer jump in one kernel per tile (ge_nn_fused.hip): reads u, writes
+// the per-rod scale and u_next = u + 64 r s out.
+struct FusedArgs {
+    const float *u;          // [batch][width]
+    const float *r;          // [batch]
+    float *scale;            // [batch], written
+    int width;
+    const void *w[6];        // packed forward weights of the six layers
+    const float *bias[6];    // padded biases
+    float *u_next;           // [batch][width]
+};
+hipError_t launch_jump_fused(const FusedArgs &a, int batch, hipStream_t s);
+
 hipError_t launch_widen(const float *u, double *d, int64_t M, hipStream_t s);
 hipError_t launch_narrow(const double *d, float *u, int64_t M, hipStream_t s);
 hipError_t launch_recheck(const float *a, const double *b, int W, int batch, double tol, int *flag,

@@ -163,6 +163,24 @@ hipError_t forward(ge_nn_s *n, const float *u, const float *r, int batch, hipStr
     return hipSuccess;
 }
 
+// u_next = u + 64 r s out by the six-layer fused kernel (u_next must not
+// overlap u)
+hipError_t fused_jump(ge_nn_s *n, const float *u, const float *r, int batch, float *u_next,
+                      hipStream_t s)
+{
+    FusedArgs a{};
+    a.u = u;
+    a.r = r;
+    a.scale = n->scale;
+    a.width = n->width;
+    for (int l = 0; l < 6; ++l) {
+        a.w[l] = n->wf[l];
+        a.bias[l] = n->bf[l];
+    }
+    a.u_next = u_next;
+    return launch_jump_fused(a, batch, s);
+}
+
 int wgrad_blocks(ge_nn_s *n, int batch)
 {
     const int64_t nseg = (int64_t)batch * (n->width / 128);
@@ -335,8 +353,12 @@ ge_status ge_nn_jump(ge_nn_t n, const float *u, const float *r, int32_t batch, f
     if (st != GE_OK) return st;
     if (!u || !r || !u_next) return fail(GE_ERR_INVALID, "ge_nn_jump: NULL argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = forward(n, u, r, batch, s, false);
-    if (e == hipSuccess) e = launch_jump(u, n->out, r, n->scale, n->width, batch, u_next, s);
+    const size_t M = (size_t)batch * n->width;
+    // the fused kernel reads neighbouring tiles' points: never in place
+    float *dst = u_next == u ? n->unn : u_next;
+    hipError_t e = fused_jump(n, u, r, batch, dst, s);
+    if (e == hipSuccess && dst != u_next)
+        e = hipMemcpyAsync(u_next, dst, M * 4, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_jump: %s", hipGetErrorString(e));
 }
 
@@ -422,20 +444,22 @@ ge_status ge_nn_advance(ge_nn_t n, ge_batch_t ge, void *ge_ws, float *u, const f
         const int nj = std::min(check, njumps - j0);
         const int64_t lev0 = step0 + 64LL * j0;
         e = hipMemcpyAsync(n->save, u, M * 4, hipMemcpyDeviceToDevice, s);
+        // jumps ping-pong between u and unn (the fused kernel is never in place)
+        float *cur = u, *spare = n->unn;
         for (int j = 0; j + 1 < nj && e == hipSuccess; ++j) {
-            e = forward(n, u, r, batch, s, false);
-            if (e == hipSuccess) e = launch_jump(u, n->out, r, n->scale, W, batch, u, s);
+            e = fused_jump(n, cur, r, batch, spare, s);
+            std::swap(cur, spare);
         }
-        // the window's last jump, by the network and by 64 GE levels
-        if (e == hipSuccess) e = forward(n, u, r, batch, s, false);
-        if (e == hipSuccess) e = launch_jump(u, n->out, r, n->scale, W, batch, n->unn, s);
-        if (e == hipSuccess) e = launch_widen(u, n->gev, M, s);
+        // the window's last jump, by the network (into spare) and by 64 GE
+        // levels from the same input
+        if (e == hipSuccess) e = fused_jump(n, cur, r, batch, spare, s);
+        if (e == hipSuccess) e = launch_widen(cur, n->gev, M, s);
         if (e != hipSuccess) break;
         st = ge_solve_batch(ge, n->gev, ge_ws, lev0 + 64LL * (nj - 1), 64, s);
         if (st != GE_OK) return st;
-        e = launch_recheck(n->unn, n->gev, W, batch, tol, n->flag, last_err, accepted, fallbacks,
+        e = launch_recheck(spare, n->gev, W, batch, tol, n->flag, last_err, accepted, fallbacks,
                            n->count, s);
-        if (e == hipSuccess) e = launch_select(u, n->unn, n->save, n->flag, W, batch, s);
+        if (e == hipSuccess) e = launch_select(u, spare, n->save, n->flag, W, batch, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(n->h_count, n->count, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);

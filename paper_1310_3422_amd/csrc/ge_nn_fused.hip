@@ -1,0 +1,218 @@
+// The surrogate's 64-level jump with all six layers fused: one workgroup
+// takes a tile of kFP points of one rod from u to u_next, keeping every
+// activation in LDS, so HBM sees only u (read) and u_next (written) -- the
+// layer-by-layer path writes and re-reads 128 bytes per point per layer.
+//
+// Each layer is computed on kFR = kFP + 32 rows (16 beyond each side of the
+// tile).  A layer reads its input two rows either side, so after each layer
+// the rows whose inputs were not all computed grow by two at each edge of
+// the computed range; after six layers the valid rows still cover the tile
+// with four to spare.  Rows outside the rod are set to zero after every
+// layer, which is the zero padding of the layer-by-layer path.  The
+// arithmetic (the features, the MFMA accumulation order, the epilogues and
+// the jump) is the same expression sequence as the layer-by-layer kernels,
+// so both paths give the same bits.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ge_nn.h"
+#include "ge_nn_dev.h"
+
+namespace ge {
+namespace nn {
+namespace {
+
+using namespace dev;
+
+constexpr int kFP = 480;                   // output points per workgroup
+constexpr int kFHalo = 16;                 // computed rows beyond each side
+constexpr int kFR = kFP + 2 * kFHalo;      // rows computed per layer (32 M-tiles)
+constexpr int kFWaves = 4;                 // 8 M-tiles of 16 rows per wave
+constexpr int kFMT = kFR / 16 / kFWaves;
+constexpr int kFRows = kFR + 4;            // LDS rows: computed rows plus 2 each side
+constexpr int kFXS = 72;                   // LDS row pitch (bf16): 64 channels + 16 bytes
+constexpr int kFThreads = 64 * kFWaves;
+static_assert(kFR % (16 * kFWaves) == 0, "rows per wave");
+
+// LDS row i holds position w0 - kFHalo - 2 + i.
+
+// Weights of one layer, packed [5][cout][cin] bf16, into LDS rows of kFXS.
+template <int CIN, int COUT>
+__device__ __forceinline__ void load_weights(bf16 *ws, const bf16 *wt, int tid)
+{
+    constexpr int CPR = CIN / 8;
+    for (int i = tid; i < kTaps * COUT * CPR; i += kFThreads) {
+        const int row = i / CPR, ch = (i % CPR) * 8;
+        copy16(&ws[row * kFXS + ch], &wt[row * CIN + ch]);
+    }
+}
+
+// acc[m][n] += conv of the activations with the layer's weights for the
+// wave's M-tiles: same k-outer, channel-chunk-inner order as conv_kernel.
+template <int CIN, int COUT>
+__device__ __forceinline__ void layer_mfma(const bf16 *act, const bf16 *ws, int wv, int lane,
+                                           f32x4 (&acc)[kFMT][COUT / 16])
+{
+    constexpr int NT = COUT / 16, KC = CIN / 32;
+    const int r16 = lane & 15, g4 = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < kFMT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < kTaps; ++k) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            bf16x8 bfr[NT];
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                bfr[n] = *reinterpret_cast<const bf16x8 *>(
+                    &ws[(k * COUT + 16 * n + r16) * kFXS + 32 * c + 8 * g4]);
+#pragma unroll
+            for (int m = 0; m < kFMT; ++m) {
+                // computed row q reads LDS rows q + k (q + 2 is its own row)
+                const int q = 16 * (kFMT * wv + m) + r16;
+                const bf16x8 af =
+                    *reinterpret_cast<const bf16x8 *>(&act[(q + k) * kFXS + 32 * c + 8 * g4]);
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[n], acc[m][n],
+                                                                       0, 0, 0);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
+{
+    __shared__ __attribute__((aligned(16))) bf16 act[kFRows * kFXS];
+    __shared__ __attribute__((aligned(16))) bf16 ws[kTaps * 64 * kFXS];
+    __shared__ float bias[64];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int b = blockIdx.y;
+    const int W = a.width;
+    const int w0 = blockIdx.x * kFP;
+    const int64_t base = (int64_t)b * W;
+    const float *ub = a.u + base;
+    const float sc = a.scale[b];
+    const float rb = a.r[b];
+    const float rn = (rb - 1.25f) / 0.75f;
+
+    // features of every LDS row (zero outside the rod), channels 2..63 zero
+    for (int i = tid; i < kFRows; i += kFThreads) {
+        const int w = w0 - kFHalo - 2 + i;
+        bf16 *row = &act[i * kFXS];
+        float f0 = 0.f, f1 = 0.f;
+        if (w >= 0 && w < W) {
+            const float um = w > 0 ? ub[w - 1] : 0.f, up = w < W - 1 ? ub[w + 1] : 0.f;
+            const float d = (um - ub[w]) + (up - ub[w]);
+            f0 = d / sc;
+            f1 = rn;
+        }
+        row[0] = f2bf(f0);
+        row[1] = f2bf(f1);
+        for (int c = 2; c < 64; ++c) row[c] = f2bf(0.f);
+    }
+    load_weights<32, 64>(ws, static_cast<const bf16 *>(a.w[0]), tid);
+    if (tid < 64) bias[tid] = a.bias[0][tid];
+    __syncthreads();
+
+    const int r16 = lane & 15, g4 = lane >> 4;
+    // layers 1..5 (GELU; residual from layer 2 on)
+    {
+        f32x4 acc[kFMT][4];
+        layer_mfma<32, 64>(act, ws, wv, lane, acc);
+#pragma unroll 1
+        for (int l = 0; l < 5; ++l) {
+            __syncthreads();   // every wave has finished reading act and ws
+            float bl[4];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) bl[n] = bias[16 * n + r16];
+            // the next layer's weights load while the epilogue runs
+            if (l < 4)
+                load_weights<64, 64>(ws, static_cast<const bf16 *>(a.w[l + 1]), tid);
+            else
+                load_weights<64, 16>(ws, static_cast<const bf16 *>(a.w[5]), tid);
+#pragma unroll
+            for (int m = 0; m < kFMT; ++m) {
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int q = 16 * (kFMT * wv + m) + 4 * g4 + j;   // computed row
+                        const int w = w0 - kFHalo + q;
+                        const int ch = 16 * n + r16;
+                        bf16 *dst = &act[(q + 2) * kFXS + ch];
+                        float v = acc[m][n][j] + bl[n];
+                        float h = gelu(v);
+                        if (l > 0) h += bf2f(*dst);
+                        *dst = (w >= 0 && w < W) ? f2bf(h) : f2bf(0.f);
+                    }
+                }
+            }
+            __syncthreads();   // activations and weights are in place
+            if (tid < 64) bias[tid] = (l < 4) ? a.bias[l + 1][tid] : (tid < 16 ? a.bias[5][tid] : 0.f);
+            __syncthreads();
+            if (l < 4) layer_mfma<64, 64>(act, ws, wv, lane, acc);
+        }
+    }
+    // layer 6 (64 -> 1, padded to 16 outputs) and the jump
+    f32x4 acc6[kFMT][1];
+    layer_mfma<64, 16>(act, ws, wv, lane, acc6);
+    if (r16 == 0) {
+        const float b0 = bias[0];
+        const float amp = 64.0f * rb * sc;
+#pragma unroll
+        for (int m = 0; m < kFMT; ++m)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int q = 16 * (kFMT * wv + m) + 4 * g4 + j;
+                const int p = q - kFHalo;                       // point within the tile
+                const int w = w0 + p;
+                if (p >= 0 && p < kFP && w < W) {
+                    const float out = acc6[m][0][j] + b0;
+                    a.u_next[base + w] = ub[w] + amp * out;
+                }
+            }
+    }
+}
+
+// Per-rod scale: RMS of the rod's second differences (zero walls), in the
+// same summation order as features_kernel.
+__global__ __launch_bounds__(256) void rod_scale_kernel(const float *u, int W, float *scale)
+{
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const float *ub = u + (int64_t)b * W;
+    __shared__ float red[256];
+    float ss = 0.f;
+    for (int i = tid; i < W; i += 256) {
+        const float um = i > 0 ? ub[i - 1] : 0.f, up = i < W - 1 ? ub[i + 1] : 0.f;
+        const float d = (um - ub[i]) + (up - ub[i]);
+        ss += d * d;
+    }
+    red[tid] = ss;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) scale[b] = sqrtf(red[0] / W) + 1e-30f;
+}
+
+}  // namespace
+
+hipError_t launch_jump_fused(const FusedArgs &a, int batch, hipStream_t s)
+{
+    hipLaunchKernelGGL(rod_scale_kernel, dim3(batch), dim3(256), 0, s, a.u, a.width, a.scale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((a.width + kFP - 1) / kFP, batch);
+    hipLaunchKernelGGL(jump_fused_kernel, grid, dim3(kFThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace ge

@@ -110,10 +110,13 @@ def moving_wall_rod(n, r=4.0, nsteps=5000, step0=0):
         src_b=x * (1.0 - x), src_a=np.exp(-(t[:-1] + 0.5 * tau)))
 
 
-def surrogate_rods(seed, nrods, n=4096, rmin=0.5, rmax=2.0):
+def surrogate_rods(seed, nrods, n=4096, rmin=0.5, rmax=2.0, noise=None):
     """Initial values and mesh ratios for surrogate training/evaluation:
     draws r (nrods) then z (nrods x 16); zero walls.  ``seed`` may be an int
-    or a sequence of ints (a data set split into seeded chunks)."""
+    or a sequence of ints (a data set split into seeded chunks).  With
+    ``noise = (lo, hi)`` each rod also gets white noise of relative size eps,
+    eps log-uniform in [lo, hi] times the rod's RMS, drawn after z (eps, then
+    the noise values)."""
     rng = np.random.default_rng(seed)
     r = rng.uniform(rmin, rmax, nrods)
     z = rng.standard_normal((nrods, NMODES))
@@ -121,4 +124,9 @@ def surrogate_rods(seed, nrods, n=4096, rmin=0.5, rmax=2.0):
     k = np.arange(1, NMODES + 1, dtype=np.float64)
     basis = np.sin(np.pi * np.outer(k, x))          # [16, n]
     u0 = (z / (k * k)) @ basis                       # [nrods, n]
+    if noise is not None:
+        lo, hi = noise
+        eps = np.exp(rng.uniform(np.log(lo), np.log(hi), nrods))
+        rms = np.sqrt(np.mean(u0 * u0, axis=1))
+        u0 = u0 + (eps * rms)[:, None] * rng.standard_normal((nrods, n))
     return r, u0

@@ -36,9 +36,9 @@ class Trajectories:
     after every 64 levels: states[j] holds level 64 j (j = 0..njumps) of all
     rods, back to back."""
 
-    def __init__(self, seed, nrods, width=4096, njumps=8, rmin=0.5, rmax=2.0):
+    def __init__(self, seed, nrods, width=4096, njumps=8, rmin=0.5, rmax=2.0, noise=None):
         torch = _torch()
-        r, u0 = inputs.surrogate_rods(seed, nrods, n=width, rmin=rmin, rmax=rmax)
+        r, u0 = inputs.surrogate_rods(seed, nrods, n=width, rmin=rmin, rmax=rmax, noise=noise)
         self.nrods, self.width, self.njumps = nrods, width, njumps
         self.r64 = r
         self.r = torch.from_numpy(r.astype(np.float32)).cuda()
@@ -60,7 +60,8 @@ class Trainer:
     """Adam on minibatches of (u, u after 64 levels) pairs drawn from
     trajectory chunks; chunk c of a data set with seed s uses seed [s, c]."""
 
-    def __init__(self, net, seed=4, ntraj=2048, chunk=1024, njumps=8, minibatch=64):
+    def __init__(self, net, seed=4, ntraj=2048, chunk=1024, njumps=8, minibatch=64,
+                 noise=None):
         self.net = net
         self.seed, self.ntraj, self.chunk = seed, ntraj, min(chunk, ntraj)
         self.njumps, self.minibatch = njumps, minibatch
@@ -68,7 +69,7 @@ class Trainer:
         self.chunks = []
         for c in range((ntraj + self.chunk - 1) // self.chunk):
             nr = min(self.chunk, ntraj - c * self.chunk)
-            self.chunks.append(Trajectories([seed, c], nr, net.width, njumps))
+            self.chunks.append(Trajectories([seed, c], nr, net.width, njumps, noise=noise))
         torch = _torch()
         B, W = minibatch, net.width
         self.u = torch.empty(B * W, dtype=torch.float32, device="cuda")
@@ -137,6 +138,26 @@ def evaluate(net, seed=41, nrods=256, width=None, start_jump=1):
         res[k] = {"rel_l2": rel_l2_rows(v, ref),
                   "inc_rel_l2": rel_l2_rows(v - u_np, ref - u_np)}
     return res
+
+
+def rollout(net, seed=41, nrods=256, width=None, njumps=8, noise=None):
+    """Per-rod rel-L2 distance from the FP64 GE sweep after each of njumps
+    surrogate jumps applied in a row (no re-check), from level 0."""
+    torch = _torch()
+    width = width or net.width
+    tr = Trajectories(seed, nrods, width, njumps=njumps, noise=noise)
+    u = tr.rods(0).contiguous().view(-1).clone()
+    nxt = torch.empty_like(u)
+    out = []
+    for j in range(1, njumps + 1):
+        for i in range(0, nrods, net.max_batch):
+            b = min(net.max_batch, nrods - i)
+            sl = slice(i * width, (i + b) * width)
+            net.jump(u[sl], tr.r[i:i + b].contiguous(), out=nxt[sl])
+        u, nxt = nxt, u
+        ref = tr.rods(j).cpu().numpy()
+        out.append(rel_l2_rows(u.view(nrods, width).cpu().numpy(), ref))
+    return np.stack(out)        # [njumps, nrods]
 
 
 def advance_with_recheck(net, u, r, njumps, ge_batch=None, r64=None, check=8, tol=1e-4,

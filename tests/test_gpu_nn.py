@@ -100,19 +100,24 @@ def test_forward_matches_oracle(width, batch):
     assert rel_l2(got, exact) < 20 * BF16_FLIP_TOL
 
 
-def test_jump_applies_the_scaled_increment():
-    width, batch = 512, 2
+@pytest.mark.parametrize("width,batch", [(512, 2), (4096, 3)])
+def test_fused_jump_is_the_layered_forward_plus_the_scaled_increment(width, batch):
+    """The six-layer fused jump gives the bits of the layer-by-layer forward
+    pass combined as u + (64 r s) out in FP32, in place or not (512 points:
+    a full and a ragged tile of the fused kernel)."""
     params = fp32_params(8)
     r, u, _ = rods(41, batch, width, levels=0)
     net = make_net(width, batch, params)
     out, scale = net.forward(dev(u), dev(r))
     un = net.jump(dev(u), dev(r))
+    ui = dev(u)
+    net.jump(ui, dev(r), out=ui)
     torch.cuda.synchronize()
-    o = out.cpu().numpy().reshape(batch, width).astype(np.float64)
-    sc = scale.cpu().numpy().astype(np.float64)
-    want = u.astype(np.float64) + 64.0 * r.astype(np.float64)[:, None] * sc[:, None] * o
-    np.testing.assert_allclose(un.cpu().numpy().reshape(batch, width), want, rtol=0,
-                               atol=4e-7 * np.abs(u).max())
+    o = out.cpu().numpy().reshape(batch, width)
+    amp = (np.float32(64.0) * r) * scale.cpu().numpy()
+    want = u + amp[:, None] * o
+    np.testing.assert_array_equal(un.cpu().numpy().reshape(batch, width), want)
+    np.testing.assert_array_equal(ui.cpu().numpy().reshape(batch, width), want)
 
 
 def test_loss_and_gradients_match_oracle():

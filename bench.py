@@ -33,9 +33,13 @@ R = 2.0
 LEVELS = 10000
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 # VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s
-# (the published 78.6 TFLOP/s FP64 / 157.3 TFLOP/s packed-FP32 vector peaks
-# count every op as a fused multiply-add, 2 flops, and FP32 as packed pairs).
+# for FP64 (the published 78.6 TFLOP/s FP64 vector peak counts each op as a
+# fused multiply-add, 2 flops); FP32 at the published 157.3 TFLOP/s vector
+# rate, twice that (the FP32 sweep, which has no packed instructions, ran
+# above the single rate on the box, so the single rate is no bound for it).
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+VALU_LANE_OPS_BY_PREC = {"fp64": VALU_LANE_OPS, "fp32": 2 * VALU_LANE_OPS,
+                         "fp32c": 2 * VALU_LANE_OPS}
 # per update: algorithmic flops (fma = 2) and the fewest VALU instructions the
 # form can be written in -- FP64: 2 subtractions + 2 fma; FP32: 2 sub + mul +
 # fma + add (increment first); pair: 5 for D, mul + fma, 4 for the Kahan add
@@ -260,7 +264,7 @@ def main():
     kernel_s = gpu_s / nl
     upd_per_launch = n * LEVELS / (nl / args.steps)
     flops = FLOPS_PER_UPDATE[prec] * upd_per_launch
-    peak_tf = VALU_LANE_OPS * FLOPS_PER_UPDATE[prec] / VALU_PER_UPDATE[prec] / 1e12
+    peak_tf = VALU_LANE_OPS_BY_PREC[prec] * FLOPS_PER_UPDATE[prec] / VALU_PER_UPDATE[prec] / 1e12
     achieved_tf = flops / kernel_s / 1e12
     hbm_bytes = 2 * BYTES_PER_POINT[prec] * n      # one read + one write per launch
     tkey = f"{prec}_n{n}_k{cfg['tile']}_w{cfg['waves']}_d{cfg['depth']}"
@@ -268,7 +272,7 @@ def main():
         "bound": "alu", "achieved": round(achieved_tf, 3), "peak": round(peak_tf, 2),
         "unit": "TFLOP/s", "frac": round(achieved_tf / peak_tf, 4),
         "traffic": recorded_traffic(tkey),
-        "peak_basis": f"VALU issue {VALU_LANE_OPS:.3g} lane-ops/s x {FLOPS_PER_UPDATE[prec]} "
+        "peak_basis": f"VALU issue {VALU_LANE_OPS_BY_PREC[prec]:.3g} lane-ops/s x {FLOPS_PER_UPDATE[prec]} "
                       f"flops / {VALU_PER_UPDATE[prec]} VALU ops per update",
         "kernel": f"tile_kernel<{'double' if prec == 'fp64' else 'float'},{cfg['tile']},"
                   f"{cfg['waves']},{'comp' if prec == 'fp32c' else 'plain'}>",

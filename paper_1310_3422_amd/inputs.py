@@ -110,19 +110,27 @@ def moving_wall_rod(n, r=4.0, nsteps=5000, step0=0):
         src_b=x * (1.0 - x), src_a=np.exp(-(t[:-1] + 0.5 * tau)))
 
 
-def surrogate_rods(seed, nrods, n=4096, rmin=0.5, rmax=2.0, noise=None):
+def surrogate_rods(seed, nrods, n=4096, rmin=0.5, rmax=2.0, noise=None, modes=None):
     """Initial values and mesh ratios for surrogate training/evaluation:
     draws r (nrods) then z (nrods x 16); zero walls.  ``seed`` may be an int
-    or a sequence of ints (a data set split into seeded chunks).  With
-    ``noise = (lo, hi)`` each rod also gets white noise of relative size eps,
-    eps log-uniform in [lo, hi] times the rod's RMS, drawn after z (eps, then
-    the noise values)."""
+    or a sequence of ints (a data set split into seeded chunks).
+
+    ``modes = (lo, hi)`` widens the spectrum: z is drawn as nrods x hi, then
+    each rod's cutoff K, log-uniform in [lo, hi], keeps modes 1..K (the
+    coefficients z_k / k^2 give every mode the same second-difference
+    amplitude, so short waves weigh as much as long ones in the features).
+    ``noise = (lo, hi)`` then adds white noise of relative size eps, eps
+    log-uniform in [lo, hi] times the rod's RMS (eps, then the values)."""
     rng = np.random.default_rng(seed)
     r = rng.uniform(rmin, rmax, nrods)
-    z = rng.standard_normal((nrods, NMODES))
+    kmax = NMODES if modes is None else int(modes[1])
+    z = rng.standard_normal((nrods, kmax))
+    if modes is not None:
+        cut = np.exp(rng.uniform(np.log(modes[0]), np.log(modes[1]), nrods))
+        z = np.where(np.arange(1, kmax + 1)[None, :] <= cut[:, None], z, 0.0)
     x = abscissae(n)
-    k = np.arange(1, NMODES + 1, dtype=np.float64)
-    basis = np.sin(np.pi * np.outer(k, x))          # [16, n]
+    k = np.arange(1, kmax + 1, dtype=np.float64)
+    basis = np.sin(np.pi * np.outer(k, x))          # [kmax, n]
     u0 = (z / (k * k)) @ basis                       # [nrods, n]
     if noise is not None:
         lo, hi = noise

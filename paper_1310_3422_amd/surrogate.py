@@ -36,9 +36,11 @@ class Trajectories:
     after every 64 levels: states[j] holds level 64 j (j = 0..njumps) of all
     rods, back to back."""
 
-    def __init__(self, seed, nrods, width=4096, njumps=8, rmin=0.5, rmax=2.0, noise=None):
+    def __init__(self, seed, nrods, width=4096, njumps=8, rmin=0.5, rmax=2.0, noise=None,
+                 modes=None):
         torch = _torch()
-        r, u0 = inputs.surrogate_rods(seed, nrods, n=width, rmin=rmin, rmax=rmax, noise=noise)
+        r, u0 = inputs.surrogate_rods(seed, nrods, n=width, rmin=rmin, rmax=rmax, noise=noise,
+                                      modes=modes)
         self.nrods, self.width, self.njumps = nrods, width, njumps
         self.r64 = r
         self.r = torch.from_numpy(r.astype(np.float32)).cuda()
@@ -61,7 +63,7 @@ class Trainer:
     trajectory chunks; chunk c of a data set with seed s uses seed [s, c]."""
 
     def __init__(self, net, seed=4, ntraj=2048, chunk=1024, njumps=8, minibatch=64,
-                 noise=None):
+                 noise=None, modes=None):
         self.net = net
         self.seed, self.ntraj, self.chunk = seed, ntraj, min(chunk, ntraj)
         self.njumps, self.minibatch = njumps, minibatch
@@ -69,7 +71,8 @@ class Trainer:
         self.chunks = []
         for c in range((ntraj + self.chunk - 1) // self.chunk):
             nr = min(self.chunk, ntraj - c * self.chunk)
-            self.chunks.append(Trajectories([seed, c], nr, net.width, njumps, noise=noise))
+            self.chunks.append(Trajectories([seed, c], nr, net.width, njumps, noise=noise,
+                                            modes=modes))
         torch = _torch()
         B, W = minibatch, net.width
         self.u = torch.empty(B * W, dtype=torch.float32, device="cuda")
@@ -140,12 +143,12 @@ def evaluate(net, seed=41, nrods=256, width=None, start_jump=1):
     return res
 
 
-def rollout(net, seed=41, nrods=256, width=None, njumps=8, noise=None):
+def rollout(net, seed=41, nrods=256, width=None, njumps=8, noise=None, modes=None):
     """Per-rod rel-L2 distance from the FP64 GE sweep after each of njumps
     surrogate jumps applied in a row (no re-check), from level 0."""
     torch = _torch()
     width = width or net.width
-    tr = Trajectories(seed, nrods, width, njumps=njumps, noise=noise)
+    tr = Trajectories(seed, nrods, width, njumps=njumps, noise=noise, modes=modes)
     u = tr.rods(0).contiguous().view(-1).clone()
     nxt = torch.empty_like(u)
     out = []

@@ -93,6 +93,10 @@ typedef struct {
     const void *src_b;  /* device, n values of the state's element type       */
                         /* (float for both FP32 forms): b(x_i); NULL = no     */
                         /* source.  Must stay valid while the plan is used.   */
+    int32_t schedule;   /* 0 = library choice; 1 = one workgroup per tile per */
+                        /* launch; 2 = persistent single-wave workgroups that */
+                        /* sweep several tiles each, loading the next tile    */
+                        /* during the current one (waves must be 1)           */
 } ge_desc;
 
 /* Bytes of device workspace a ge_step_n call on this problem needs (the
@@ -136,6 +140,10 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0,
  * waves per workgroup, and the halo width it implies. */
 ge_status ge_plan_config(ge_plan_t plan, int32_t *tile, int32_t *depth,
                          int32_t *waves, int32_t *halo);
+
+/* The schedule the plan's multi-tile launches use: 1 = one workgroup per
+ * tile, 2 = persistent single-wave workgroups; -1 for NULL. */
+int32_t ge_plan_schedule(ge_plan_t plan);
 
 /* Convert between the compensated pair and FP64 (checkpoints of a
  * GE_FP32_COMP run).  pair: device, GE_FP32_COMP layout of n points; x:

@@ -94,6 +94,7 @@ struct ge_plan_s {
     int64_t core;
     int64_t ntiles;
     bool single;   // the whole rod fits one window: no halo, all levels per launch
+    bool persistent;  // multi-tile launches by the persistent single-wave kernel
     double g_left, g_right;
     const void *src_b;
     double c1, c2, cs, e1, e2, es, tau, h;
@@ -165,6 +166,11 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
     if (!ge::tile_config_supported(prec, tile, waves))
         return fail(GE_ERR_INVALID, "ge_plan: tile %d with %d waves is not built for precision %d",
                     tile, waves, prec);
+    if (d->schedule < 0 || d->schedule > 2)
+        return fail(GE_ERR_INVALID, "ge_plan: schedule %d unknown", d->schedule);
+    if (d->schedule == 2 && !(waves == 1 && ge::persistent_supported(prec, tile)))
+        return fail(GE_ERR_INVALID,
+                    "ge_plan: the persistent schedule needs one wave and a built tile (%d)", tile);
 
     ge_plan_s *p = new (std::nothrow) ge_plan_s();
     if (!p)
@@ -200,6 +206,7 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
         }
         p->ntiles = (p->n + p->core - 1) / p->core;
     }
+    p->persistent = !p->single && p->ntiles >= 3 && d->schedule == 2;
     const double r = p->r;
     p->h = 1.0 / (double)(p->n + 1);
     p->tau = r * p->h * p->h;
@@ -226,6 +233,12 @@ ge_status ge_plan_config(ge_plan_t plan, int32_t *tile, int32_t *depth, int32_t 
     if (waves) *waves = plan->waves;
     if (halo) *halo = plan->halo;
     return GE_OK;
+}
+
+int32_t ge_plan_schedule(ge_plan_t plan)
+{
+    if (!plan) return -1;
+    return plan->persistent ? 2 : 1;
 }
 
 ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int64_t nsteps,
@@ -308,7 +321,9 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
         a.gl_t = g_left_t ? g_left_t + done : nullptr;
         a.gr_t = g_right_t ? g_right_t + done : nullptr;
         a.src_a = src_a_t ? src_a_t + done : nullptr;
-        hipError_t e = ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, a, st);
+        hipError_t e = plan->persistent
+                            ? ge::launch_tiles_persistent(plan->prec, plan->tile, src, a, st)
+                            : ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, a, st);
         if (e != hipSuccess)
             return hip_fail(e, "ge_step_n: launch");
         done += lev;

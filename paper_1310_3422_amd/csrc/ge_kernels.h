@@ -39,6 +39,12 @@ bool tile_config_supported(int prec, int k, int nw);
 hipError_t launch_tiles(int prec, int k, int nw, bool src, const TileArgs &a,
                         hipStream_t stream);
 
+// Persistent single-wave form (tile_persistent_kernel): interior tiles
+// round-robin with the next tile's load overlapping the current sweep.
+bool persistent_supported(int prec, int k);
+hipError_t launch_tiles_persistent(int prec, int k, bool src, const TileArgs &a,
+                                   hipStream_t stream);
+
 // Elementwise conversions for the compensated pair.
 hipError_t launch_comp_to_fp64(const float *pair, double *x, int64_t n, hipStream_t s);
 hipError_t launch_comp_from_fp64(const double *x, float *pair, int64_t n, hipStream_t s);

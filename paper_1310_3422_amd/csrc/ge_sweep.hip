@@ -17,8 +17,36 @@ namespace {
 
 using namespace dev;
 
+// The lane's points of the window starting at ws (and their compensation
+// and source profile where the form has them); guarded at a wall.
+template <typename T, int K, bool COMP, bool SRC, bool WALL>
+__device__ __forceinline__ void load_tile(const TileArgs &a, int64_t ws, T (&s)[K], T (&e)[K],
+                                          T (&b)[K])
+{
+    const int64_t g0 = ws + (int64_t)threadIdx.x * K;
+    const T *in_s = static_cast<const T *>(a.in);
+    const T *in_e = in_s + a.estride;
+    const T *srcb = static_cast<const T *>(a.src_b);
+    if constexpr (WALL) {
+        load_lane_guarded<T, K>(in_s + g0, g0, a.n, s);
+        if constexpr (COMP) load_lane_guarded<T, K>(in_e + g0, g0, a.n, e);
+        if constexpr (SRC) load_lane_guarded<T, K>(srcb + g0, g0, a.n, b);
+    } else {
+        load_lane<T, K>(in_s + g0, s);
+        if constexpr (COMP) load_lane<T, K>(in_e + g0, e);
+        if constexpr (SRC) load_lane<T, K>(srcb + g0, b);
+    }
+    if constexpr (!COMP) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) e[j] = T(0);
+    }
+}
+
+// Advance the loaded window of tile t (start ws) by the launch's levels and
+// store its core.
 template <typename T, int K, int NW, bool COMP, bool SRC, bool WALL>
-__device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t ws)
+__device__ __forceinline__ void sweep_tile(const TileArgs &a, int64_t t, int64_t ws, T (&s)[K],
+                                           T (&e)[K], const T (&b)[K])
 {
     constexpr int W = NW * kWave * K;
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -30,26 +58,8 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
     const int64_t core_hi = min(core_lo + a.core, n);
     const int64_t g0 = ws + (int64_t)tid * K;       // global index of my first point
 
-    const T *in_s = static_cast<const T *>(a.in);
     T *out_s = static_cast<T *>(a.out);
-    const T *in_e = in_s + a.estride;
     T *out_e = out_s + a.estride;
-    const T *srcb = static_cast<const T *>(a.src_b);
-
-    T s[K], e[K], b[K];
-    if constexpr (WALL) {
-        load_lane_guarded<T, K>(in_s + g0, g0, n, s);
-        if constexpr (COMP) load_lane_guarded<T, K>(in_e + g0, g0, n, e);
-        if constexpr (SRC) load_lane_guarded<T, K>(srcb + g0, g0, n, b);
-    } else {
-        load_lane<T, K>(in_s + g0, s);
-        if constexpr (COMP) load_lane<T, K>(in_e + g0, e);
-        if constexpr (SRC) load_lane<T, K>(srcb + g0, b);
-    }
-    if constexpr (!COMP) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) e[j] = T(0);
-    }
 
     __shared__ T xs[2][NW][4];
     __shared__ T xe[2][NW][4];
@@ -180,6 +190,14 @@ __device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t w
     }
 }
 
+template <typename T, int K, int NW, bool COMP, bool SRC, bool WALL>
+__device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t ws)
+{
+    T s[K], e[K], b[K];
+    load_tile<T, K, COMP, SRC, WALL>(a, ws, s, e, b);
+    sweep_tile<T, K, NW, COMP, SRC, WALL>(a, t, ws, s, e, b);
+}
+
 template <typename T, int K, int NW, bool COMP, bool SRC>
 __global__ __launch_bounds__(NW *kWave) void tile_kernel(TileArgs a)
 {
@@ -196,6 +214,90 @@ __global__ __launch_bounds__(NW *kWave) void tile_kernel(TileArgs a)
         run_tile<T, K, NW, COMP, SRC, true>(a, t, ws);
     else
         run_tile<T, K, NW, COMP, SRC, false>(a, t, ws);
+}
+
+// First tile whose window reaches the right wall (tiles from there on, and
+// tile 0, take the wall path).
+__device__ __host__ inline int64_t first_right_wall_tile(const TileArgs &a, int64_t W)
+{
+    const int64_t need = a.n + a.halo - W;       // t * core >= need
+    int64_t t = need <= 0 ? 1 : (need + a.core - 1) / a.core;
+    if (t < 1) t = 1;
+    return t < a.ntiles ? t : a.ntiles;
+}
+
+// Persistent form for single-wave windows.  The first nint workgroups sweep
+// the interior tiles round-robin, each loading its next tile while the
+// current one advances, so the loads hide behind the levels; the remaining
+// workgroups take one wall tile each.  Consecutive interior tiles are dealt
+// to the same XCD, as in tile_kernel.
+template <typename T, int K, bool COMP, bool SRC>
+__global__ __launch_bounds__(kWave) void tile_persistent_kernel(TileArgs a, int nint)
+{
+    constexpr int64_t W = kWave * K;
+    const int64_t tw = first_right_wall_tile(a, W);
+    const int g = blockIdx.x;
+    if (g >= nint) {
+        const int64_t t = g == nint ? 0 : tw + (g - nint - 1);
+        if (t < a.ntiles && (t == 0 || t >= tw))
+            run_tile<T, K, 1, COMP, SRC, true>(a, t, t == 0 ? 0 : t * a.core - a.halo);
+        return;
+    }
+    const int per = nint / 8;
+    const int gx = (g % 8) * per + g / 8;        // XCD-aware order (nint is a multiple of 8)
+    int64_t t = 1 + gx;
+    if (t >= tw)
+        return;
+    // every tile's values reach the sweep registers by a copy from the
+    // prefetch registers, so the loads pending during a sweep are only the
+    // next tile's and the sweep never waits for them
+    T s[K], e[K], b[K], ns[K], ne[K], nb[K];
+    load_tile<T, K, COMP, SRC, false>(a, t * a.core - a.halo, ns, ne, nb);
+    for (;;) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            s[j] = ns[j];
+            e[j] = ne[j];
+            b[j] = nb[j];
+        }
+        const int64_t tn = t + nint;
+        if (tn < tw)
+            load_tile<T, K, COMP, SRC, false>(a, tn * a.core - a.halo, ns, ne, nb);
+        sweep_tile<T, K, 1, COMP, SRC, false>(a, t, t * a.core - a.halo, s, e, b);
+        if (tn >= tw)
+            break;
+        t = tn;
+    }
+}
+
+template <typename T, int K, bool COMP, bool SRC>
+hipError_t launch_persistent(const TileArgs &a, hipStream_t stream)
+{
+    // resident single-wave workgroups per CU for this kernel, and CUs
+    static int per_cu = 0, ncu = 0;
+    if (per_cu == 0) {
+        int dev = 0, nb = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, tile_persistent_kernel<T, K, COMP, SRC>, kWave, 0) != hipSuccess ||
+            nb < 1 || ncu < 1)
+            return hipErrorInvalidValue;
+        per_cu = nb;
+    }
+    constexpr int64_t W = kWave * K;
+    const int64_t tw = first_right_wall_tile(a, W);
+    const int64_t interior = tw - 1;
+    const int64_t walls = 1 + (a.ntiles - tw);
+    // as many workgroups as stay resident, trimmed so that every one gets
+    // the same number of tiles (to one), in multiples of 8
+    const int64_t cap = (int64_t)per_cu * ncu;
+    const int64_t rounds = (interior + cap - 1) / cap;
+    int64_t nint = (interior + rounds - 1) / rounds;
+    nint = (nint + 7) / 8 * 8;
+    hipLaunchKernelGGL((tile_persistent_kernel<T, K, COMP, SRC>), dim3((unsigned)(nint + walls)),
+                       dim3(kWave), 0, stream, a, (int)nint);
+    return hipGetLastError();
 }
 
 template <typename T, int K, int NW, bool COMP, bool SRC>
@@ -246,6 +348,34 @@ __global__ void comp_from_fp64_kernel(const double *__restrict__ x, float *__res
 }  // namespace
 
 int64_t comp_offset(int64_t n);
+
+hipError_t launch_tiles_persistent(int prec, int k, bool src, const TileArgs &a,
+                                   hipStream_t stream)
+{
+#define GE_P(T, KK, C) \
+    return src ? launch_persistent<T, KK, C, true>(a, stream) : launch_persistent<T, KK, C, false>(a, stream)
+    switch (prec) {
+    case kFP64:
+        if (k == 16) GE_P(double, 16, false);
+        if (k == 32) GE_P(double, 32, false);
+        break;
+    case kFP32:
+        if (k == 16) GE_P(float, 16, false);
+        if (k == 32) GE_P(float, 32, false);
+        break;
+    case kFP32C:
+        if (k == 16) GE_P(float, 16, true);
+        break;
+    }
+#undef GE_P
+    return hipErrorInvalidValue;
+}
+
+bool persistent_supported(int prec, int k)
+{
+    return (prec == kFP64 && (k == 16 || k == 32)) || (prec == kFP32 && (k == 16 || k == 32)) ||
+           (prec == kFP32C && k == 16);
+}
 
 bool tile_config_supported(int prec, int k, int nw)
 {

@@ -26,7 +26,7 @@ _dbl = ctypes.c_double
 class GeDesc(ctypes.Structure):
     _fields_ = [("n", _i64), ("r", _dbl), ("precision", _i32), ("tile", _i32),
                 ("depth", _i32), ("waves", _i32), ("g_left", _dbl),
-                ("g_right", _dbl), ("src_b", _vp)]
+                ("g_right", _dbl), ("src_b", _vp), ("schedule", _i32)]
 
 
 class GeBatchDesc(ctypes.Structure):
@@ -64,6 +64,7 @@ _SIGS = {
     "ge_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                      ctypes.POINTER(_dbl), _vp]),
     "ge_solve_batch": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
+    "ge_plan_schedule": (_i32, [_vp]),
     "ge_nn_param_count": (_i64, []),
     "ge_nn_create": (ctypes.c_int, [ctypes.POINTER(_vp), _i32, _i32, ctypes.c_uint64]),
     "ge_nn_destroy": (None, [_vp]),
@@ -149,7 +150,7 @@ class Plan:
     """A ge_plan for one rod; ``step_n`` advances a device state tensor."""
 
     def __init__(self, n, r, precision="fp64", g_left=0.0, g_right=0.0, src_b=None,
-                 tile=0, depth=0, waves=0):
+                 tile=0, depth=0, waves=0, schedule=0):
         self.n, self.r = int(n), float(r)
         self.precision = _prec(precision)
         self._src_b = src_b   # keep the profile alive
@@ -157,7 +158,7 @@ class Plan:
             self._check_tensor(src_b, self.n, "src_b", state_dtype(self.precision))
         self.desc = GeDesc(n=self.n, r=self.r, precision=self.precision, tile=tile,
                            depth=depth, waves=waves, g_left=float(g_left),
-                           g_right=float(g_right), src_b=_ptr(src_b))
+                           g_right=float(g_right), src_b=_ptr(src_b), schedule=int(schedule))
         h = _vp()
         check(lib().ge_plan(ctypes.byref(h), ctypes.byref(self.desc)))
         self.handle = h
@@ -173,7 +174,8 @@ class Plan:
         t, d, w, h = _i32(), _i32(), _i32(), _i32()
         check(lib().ge_plan_config(self.handle, ctypes.byref(t), ctypes.byref(d),
                                    ctypes.byref(w), ctypes.byref(h)))
-        return {"tile": t.value, "depth": d.value, "waves": w.value, "halo": h.value}
+        return {"tile": t.value, "depth": d.value, "waves": w.value, "halo": h.value,
+                "schedule": int(lib().ge_plan_schedule(self.handle))}
 
     @staticmethod
     def _check_tensor(t, numel, name, dtype):

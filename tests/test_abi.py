@@ -238,3 +238,19 @@ def test_advance_and_conversions_validate_before_enqueueing():
     assert lib.ge_f64_to_f32(None, None, 5, None) == ge.GE_ERR_INVALID
     assert lib.ge_f32_to_f64(None, None, 0, None) == ge.GE_OK
     assert lib.ge_f64_to_f32(None, None, 0, None) == ge.GE_OK
+
+
+def test_plan_schedule_validation():
+    lib = ge.lib()
+    h = ctypes.c_void_p()
+    for sched, tile, waves, status in [(3, 16, 1, ge.GE_ERR_INVALID), (-1, 16, 1, ge.GE_ERR_INVALID),
+                                       (2, 16, 4, ge.GE_ERR_INVALID), (2, 8, 1, ge.GE_ERR_INVALID),
+                                       (2, 16, 1, ge.GE_OK), (1, 8, 4, ge.GE_OK)]:
+        d = ge.GeDesc(n=100000, r=2.0, precision=0, tile=tile, depth=8, waves=waves,
+                      schedule=sched)
+        st = lib.ge_plan(ctypes.byref(h), ctypes.byref(d))
+        assert st == status, (sched, tile, waves)
+        if st == ge.GE_OK:
+            assert lib.ge_plan_schedule(h) == (2 if sched == 2 else 1)
+            lib.ge_destroy(h)
+    assert lib.ge_plan_schedule(None) == -1

@@ -273,3 +273,35 @@ def test_single_rod_2p27_moving_walls_sampled(precision):
         want = oracle.window_step_n(w.u0, lo, hi, r, s, gl=w.g_left, gr=w.g_right,
                                     src_b=src_b, src_a=w.src_a)
         assert rel_l2(got[lo:hi], want) < tol, (lo, hi)
+
+
+# ------------------------------------------------- persistent schedule ----
+@pytest.mark.parametrize("precision,tile", [("fp64", 16), ("fp64", 32), ("fp32", 16),
+                                            ("fp32", 32), ("fp32c", 16)])
+def test_persistent_schedule_is_bitwise_the_per_tile_schedule(precision, tile):
+    """The persistent kernel sweeps the same tiles with the same arithmetic:
+    same bits, with walls, a source, per-level walls and the flux; rods whose
+    last tile is short put two tiles on the wall path."""
+    rng = np.random.default_rng(tile)
+    for n, depth in ((200003, 17), (64 * tile * 7 + 5, 40), (64 * tile * 3 - 1, 9)):
+        w = inputs.moving_wall_rod(n, r=3.0, nsteps=53, step0=1)
+        u0 = inputs.sine_rod(n, n) + 0.05 * rng.standard_normal(n)
+        runs = []
+        for schedule in (1, 2):
+            got, fl = run_gpu(u0, 3.0, 53, precision, step0=1, gl=w.g_left, gr=0.3,
+                              src_b=w.src_b, src_a=w.src_a, flux=True, tile=tile, waves=1,
+                              depth=depth, schedule=schedule)
+            runs.append((got, fl))
+        np.testing.assert_array_equal(runs[0][0], runs[1][0])
+        np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    plan = ge.Plan(200003, 3.0, precision, tile=tile, waves=1, depth=17, schedule=2)
+    assert plan.config()["schedule"] == 2
+
+
+def test_persistent_schedule_fp64_parity():
+    n, s = 300007, 97
+    u0 = inputs.sine_rod(n, 3) + 0.1 * np.random.default_rng(3).standard_normal(n)
+    got = run_gpu(u0, 2.0, s, "fp64", step0=0, gl=0.5, gr=-0.25, tile=16, waves=1, depth=48,
+                  schedule=2)
+    want = oracle.step_n(u0, 2.0, s, gl=0.5, gr=-0.25)
+    assert rel_l2(got, want) < 1e-12

@@ -3,18 +3,21 @@
 TEST INFRASTRUCTURE ONLY: used by the tests to check the GPU network's
 forward pass and gradients; the GPU library never calls it.
 
-The network (a reading of the unstated details, see the design doc's list of
-readings): a 1D convolutional net over the n points of a rod, channels-last
-tensors x[b, w, c].
+The network (a reading of the unstated details): a 1D convolutional net
+over the n points of a rod, channels-last tensors x[b, w, c].
 
-    layer 1 : pre1 = conv(x, W1) + b1,           h1 = gelu(pre1)        (2 -> 64)
-    layer l : pre_l = conv(h_{l-1}, W_l) + b_l,  h_l = h_{l-1} + gelu(pre_l)
+    layer 1 : pre1 = conv_1(x, W1) + b1,           h1 = gelu(pre1)       (2 -> 64)
+    layer l : pre_l = conv_l(h_{l-1}, W_l) + b_l,  h_l = h_{l-1} + gelu(pre_l)
               for l = 2..5                                             (64 -> 64)
-    layer 6 : out = conv(h5, W6) + b6                                    (64 -> 1)
+    layer 6 : out = conv_6(h5, W6) + b6                                  (64 -> 1)
 
-    conv(x, W)[b, w, o] = sum_{k=0..4} sum_i W[k, o, i] x[b, w + k - 2, i],
-    with x = 0 outside the rod (zero padding), gelu(z) = z Phi(z) with the
-    exact normal CDF Phi.
+    conv_l(x, W)[b, w, o] = sum_{k=0..4} sum_i W[k, o, i] x[b, w + (k - 2) d_l, i],
+    dilations d = (1, 2, 4, 8, 16, 1), x = 0 outside the rod (zero padding),
+    gelu(z) = z Phi(z) with the exact normal CDF Phi.  The dilations give a
+    receptive field of +-64 points: 64 levels of the sweep move a point's
+    influence about as far (at r = 2 a fifth of the increment caused by a
+    point lies more than 13 points away, which a plain kernel-5 stack of six
+    layers cannot see).
 
 Loss: mean over (b, w) of (out[b, w, 0] - t[b, w])^2.
 
@@ -35,6 +38,7 @@ import math
 import numpy as np
 
 LAYERS = [(2, 64), (64, 64), (64, 64), (64, 64), (64, 64), (64, 1)]
+DILATIONS = [1, 2, 4, 8, 16, 1]
 TAPS = 5
 
 
@@ -62,37 +66,42 @@ def gelu_grad(z):
     return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * phi
 
 
-def conv(x, w):
-    """x: (B, W, Ci), w: (5, Co, Ci) -> (B, W, Co), zero padding."""
+def conv(x, w, d=1):
+    """x: (B, W, Ci), w: (5, Co, Ci) -> (B, W, Co): taps at offsets (k - 2) d,
+    zero padding."""
     B, Wn, Ci = x.shape
-    xp = np.zeros((B, Wn + TAPS - 1, Ci))
-    xp[:, 2:2 + Wn] = x
+    pad = 2 * d
+    xp = np.zeros((B, Wn + 2 * pad, Ci))
+    xp[:, pad:pad + Wn] = x
     out = np.zeros((B, Wn, w.shape[1]))
     for k in range(TAPS):
-        out += xp[:, k:k + Wn] @ w[k].T
+        out += xp[:, k * d:k * d + Wn] @ w[k].T
     return out
 
 
-def conv_input_grad(g, w):
-    """Gradient of conv(x, w) w.r.t. x for output gradient g (B, W, Co)."""
+def conv_input_grad(g, w, d=1):
+    """Gradient of conv(x, w, d) w.r.t. x for output gradient g (B, W, Co)."""
     B, Wn, Co = g.shape
-    gp = np.zeros((B, Wn + TAPS - 1, Co))
-    gp[:, 2:2 + Wn] = g
+    pad = 2 * d
+    gp = np.zeros((B, Wn + 2 * pad, Co))
+    gp[:, pad:pad + Wn] = g
     out = np.zeros((B, Wn, w.shape[2]))
-    # x[w'] receives W[k] g[w' - k + 2]
+    # x[w'] receives W[k] g[w' - (k - 2) d]
     for k in range(TAPS):
-        out += gp[:, TAPS - 1 - k:TAPS - 1 - k + Wn] @ w[k]
+        s = (TAPS - 1 - k) * d
+        out += gp[:, s:s + Wn] @ w[k]
     return out
 
 
-def conv_weight_grad(x, g):
-    """Gradient of sum(conv(x, w) * g) w.r.t. w: (5, Co, Ci)."""
+def conv_weight_grad(x, g, d=1):
+    """Gradient of sum(conv(x, w, d) * g) w.r.t. w: (5, Co, Ci)."""
     B, Wn, Ci = x.shape
-    xp = np.zeros((B, Wn + TAPS - 1, Ci))
-    xp[:, 2:2 + Wn] = x
+    pad = 2 * d
+    xp = np.zeros((B, Wn + 2 * pad, Ci))
+    xp[:, pad:pad + Wn] = x
     gw = np.zeros((TAPS, g.shape[2], Ci))
     for k in range(TAPS):
-        gw[k] = np.einsum("bwo,bwi->oi", g, xp[:, k:k + Wn])
+        gw[k] = np.einsum("bwo,bwi->oi", g, xp[:, k * d:k * d + Wn])
     return gw
 
 
@@ -140,7 +149,7 @@ def forward(params, x, bf=False):
     for li, (w, b) in enumerate(params):
         w = r(w)
         cache["inputs"].append(h)
-        pre = conv(h, w) + b
+        pre = conv(h, w, DILATIONS[li]) + b
         if li == len(params) - 1:
             cache["pre"].append(pre)
             return pre[:, :, 0], cache
@@ -170,10 +179,10 @@ def loss_and_grads(params, x, t, bf=False):
             g_pre = g
         else:
             g_pre = r(g_h * gelu_grad(cache["pre"][li]))
-        grads[li] = (conv_weight_grad(x_in, g_pre), g_pre.sum(axis=(0, 1)))
+        grads[li] = (conv_weight_grad(x_in, g_pre, DILATIONS[li]), g_pre.sum(axis=(0, 1)))
         if li == 0:
             break
-        g_in = conv_input_grad(g_pre, w)
+        g_in = conv_input_grad(g_pre, w, DILATIONS[li])
         if 0 < li < nl - 1:
             g_in = g_h + g_in           # residual path of layer li
         g_h = r(g_in)

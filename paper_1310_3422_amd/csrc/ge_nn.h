@@ -14,6 +14,7 @@ struct ConvArgs {
     const void *w;        // bf16 [5][cout][cin]
     const float *bias;    // [cout] or null
     int width;            // points per rod, a multiple of 128
+    int dil;              // tap spacing d: taps at offsets (k - 2) d, 1 <= d <= kMaxDil
     void *pre_out;        // bf16 [..][cout]  (kEpiGelu*; null: not stored)
     void *act_out;        // bf16 [..][cout]  (kEpiGelu*)
     float *out_f32;       // f32 [batch][width] (kEpiOut)
@@ -29,9 +30,11 @@ struct WgradArgs {
     float *part;          // per-workgroup partials
     int width;
     int batch;
+    int dil;              // tap spacing of the layer
 };
 
 constexpr int kMaxWgradBlocks = 256;
+constexpr int kMaxDil = 16;         // largest tap spacing of a layer
 
 hipError_t launch_conv(int cin, int cout, int epi, const ConvArgs &a, int batch, hipStream_t s);
 hipError_t launch_wgrad(int cin, int cout, const WgradArgs &a, int blocks, hipStream_t s);
@@ -59,6 +62,7 @@ struct FusedArgs {
     int width;
     const void *w[6];        // packed forward weights of the six layers
     const float *bias[6];    // padded biases
+    int dil[6];              // tap spacings of the six layers
     float *u_next;           // [batch][width]
 };
 hipError_t launch_jump_fused(const FusedArgs &a, int batch, hipStream_t s);

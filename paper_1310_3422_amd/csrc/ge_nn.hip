@@ -33,7 +33,7 @@ constexpr int kThreads = 256;     // 4 waves, 32 positions each
 
 // ---------------------------------------------------------------------------
 // Convolution as an implicit GEMM.
-//   x   : [B][W][CIN] bf16 input
+//   x   : [B][W][CIN] bf16 input, read at offsets (k - 2) d from each output
 //   wt  : [5][COUT][CIN] bf16 weights (B operand layout: output channel rows)
 //   bias: [COUT] fp32 (may be null)
 // Epilogues (EPI):
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a)
     constexpr int XS = CIN + 8;                 // padded row (bf16 elements)
     constexpr int NT = COUT / 16;               // output channel tiles
     constexpr int KC = CIN / 32;                // 32-channel K chunks per tap
-    __shared__ __attribute__((aligned(16))) bf16 xs[(kMT + 4) * XS];
+    __shared__ __attribute__((aligned(16))) bf16 xs[(kMT + 4 * kMaxDil) * XS];
     __shared__ __attribute__((aligned(16))) bf16 ws[kTaps * COUT * XS];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -58,13 +58,14 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a)
     const int b = blockIdx.y;
     const int w0 = blockIdx.x * kMT;
     const int W = a.width;
+    const int d = a.dil;
     const bf16 *x = static_cast<const bf16 *>(a.x) + (int64_t)b * W * CIN;
 
-    // input rows w0-2 .. w0+kMT+1 (zero outside the rod), 16 bytes per copy
+    // input rows w0-2d .. w0+kMT+2d-1 (zero outside the rod), 16 bytes per copy
     constexpr int CPR = CIN / 8;                // 16-byte chunks per row
-    for (int i = tid; i < (kMT + 4) * CPR; i += kThreads) {
+    for (int i = tid; i < (kMT + 4 * d) * CPR; i += kThreads) {
         const int row = i / CPR, ch = (i % CPR) * 8;
-        const int w = w0 - 2 + row;
+        const int w = w0 - 2 * d + row;
         bf16 *dst = &xs[row * XS + ch];
         if (w >= 0 && w < W)
             copy16(dst, &x[(int64_t)w * CIN + ch]);
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a)
 #pragma unroll
             for (int m = 0; m < 2; ++m)
                 af[m] = *reinterpret_cast<const bf16x8 *>(
-                    &xs[(32 * wv + 16 * m + r16 + k) * XS + 32 * c + 8 * g4]);
+                    &xs[(32 * wv + 16 * m + r16 + k * d) * XS + 32 * c + 8 * g4]);
 #pragma unroll
             for (int n = 0; n < NT; ++n)
                 bfr[n] = *reinterpret_cast<const bf16x8 *>(
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a)
                 if constexpr (EPI == kEpiGelu || EPI == kEpiGeluRes) {
                     if (a.pre_out) static_cast<bf16 *>(a.pre_out)[o] = f2bf(v);
                     float act = gelu(v);
-                    if constexpr (EPI == kEpiGeluRes) act += bf2f(xs[(pl + 2) * XS + ch]);
+                    if constexpr (EPI == kEpiGeluRes) act += bf2f(xs[(pl + 2 * d) * XS + ch]);
                     static_cast<bf16 *>(a.act_out)[o] = f2bf(act);
                 } else if constexpr (EPI == kEpiOut) {
                     if (ch == 0) a.out_f32[rowbase + w] = v;
@@ -141,13 +142,13 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient dW[k][o][i] = sum_{b,w} g[b][w][o] x[b][w + k - 2][i] and
+// Weight gradient dW[k][o][i] = sum_{b,w} g[b][w][o] x[b][w + (k - 2) d][i] and
 // bias gradient db[o] = sum g[b][w][o].  One wave per tap (5 waves); each
 // workgroup reduces a fixed range of 128-position segments into registers
 // and writes its partial sums; wgrad_reduce adds the partials in order.
 // The GEMM runs with M = output channels, N = input channels, K = positions,
 // from LDS tiles stored transposed (positions contiguous): gT[o][p] and, per
-// tap, xT[i][p] = x[p + k - 2][i].
+// tap, xT[i][p] = x[p + (k - 2) d][i].
 constexpr int kWP = 128;               // positions per segment
 constexpr int kWS = kWP + 8;           // padded LDS row (bf16)
 
@@ -184,11 +185,11 @@ __global__ __launch_bounds__(64 * kTaps) void wgrad_kernel(WgradArgs a)
             const int p = i / COUT, o = i % COUT;
             gT[o * kWS + p] = gsrc[((int64_t)b * W + p0 + p) * COUT + o];
         }
-        // x tiles per tap, transposed and shifted: xT[k][i][p] = x[b][p0 + p + k - 2][i]
+        // x tiles per tap, transposed and shifted: xT[k][i][p] = x[b][p0 + p + (k - 2) d][i]
         for (int i = tid; i < kTaps * kWP * CIN; i += 64 * kTaps) {
             const int k = i / (kWP * CIN), rem = i % (kWP * CIN);
             const int p = rem / CIN, ci = rem % CIN;
-            const int w = p0 + p + k - 2;
+            const int w = p0 + p + (k - 2) * a.dil;
             xT[(k * CIN + ci) * kWS + p] =
                 (w >= 0 && w < W) ? xsrc[((int64_t)b * W + w) * CIN + ci] : (bf16)0.0f;
         }
@@ -457,6 +458,7 @@ __global__ void pack_kernel(const float *wm, const float *bm, int ci, int co, in
 
 hipError_t launch_conv(int cin, int cout, int epi, const ConvArgs &a, int batch, hipStream_t s)
 {
+    if (a.dil < 1 || a.dil > kMaxDil) return hipErrorInvalidValue;
     const dim3 grid(a.width / kMT, batch);
 #define GE_CONV(CI, CO, E) \
     if (cin == CI && cout == CO && epi == E) { \
@@ -474,6 +476,7 @@ hipError_t launch_conv(int cin, int cout, int epi, const ConvArgs &a, int batch,
 
 hipError_t launch_wgrad(int cin, int cout, const WgradArgs &a, int blocks, hipStream_t s)
 {
+    if (a.dil < 1 || a.dil > kMaxDil) return hipErrorInvalidValue;
 #define GE_WG(CI, CO) \
     if (cin == CI && cout == CO) { \
         hipLaunchKernelGGL((wgrad_kernel<CI, CO>), dim3(blocks), dim3(64 * kTaps), 0, s, a); \

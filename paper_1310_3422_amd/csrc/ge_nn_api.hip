@@ -23,18 +23,21 @@ struct Layer {
     int cip, cop;    // padded forward channels (input, output)
     int cod;         // padded channels of the gradient entering the layer (its output)
     int64_t off;     // offset of W[5][co][ci] then b[co] in the flat parameter array
+    int dil;         // tap spacing: the taps read offsets (k - 2) dil
 };
 
 // flat layout: for each layer in order, W[5][co][ci] then b[co]
 constexpr int64_t kOff1 = 5 * 64 * 2 + 64;
 constexpr int64_t kOffH = 5 * 64 * 64 + 64;
+// Tap spacings 1, 2, 4, 8, 16, 1: a receptive field of +-64 points, about
+// the reach of 64 levels of the sweep.
 const Layer kLayers[6] = {
-    {2, 64, 32, 64, 64, 0},
-    {64, 64, 64, 64, 64, kOff1},
-    {64, 64, 64, 64, 64, kOff1 + kOffH},
-    {64, 64, 64, 64, 64, kOff1 + 2 * kOffH},
-    {64, 64, 64, 64, 64, kOff1 + 3 * kOffH},
-    {64, 1, 64, 16, 32, kOff1 + 4 * kOffH},
+    {2, 64, 32, 64, 64, 0, 1},
+    {64, 64, 64, 64, 64, kOff1, 2},
+    {64, 64, 64, 64, 64, kOff1 + kOffH, 4},
+    {64, 64, 64, 64, 64, kOff1 + 2 * kOffH, 8},
+    {64, 64, 64, 64, 64, kOff1 + 3 * kOffH, 16},
+    {64, 1, 64, 16, 32, kOff1 + 4 * kOffH, 1},
 };
 
 int64_t layer_params(const Layer &l) { return 5LL * l.co * l.ci + l.co; }
@@ -150,6 +153,7 @@ hipError_t forward(ge_nn_s *n, const float *u, const float *r, int batch, hipStr
         a.w = n->wf[l];
         a.bias = n->bf[l];
         a.width = W;
+        a.dil = L.dil;
         if (l < 5) {
             a.pre_out = train ? n->pre[l] : nullptr;
             a.act_out = n->h[l];
@@ -176,6 +180,7 @@ hipError_t fused_jump(ge_nn_s *n, const float *u, const float *r, int batch, flo
     for (int l = 0; l < 6; ++l) {
         a.w[l] = n->wf[l];
         a.bias[l] = n->bf[l];
+        a.dil[l] = kLayers[l].dil;
     }
     a.u_next = u_next;
     return launch_jump_fused(a, batch, s);
@@ -195,7 +200,7 @@ hipError_t backward(ge_nn_s *n, int batch, hipStream_t s)
     // layer 6: weight gradient from h5 and the loss gradient; input gradient
     {
         const Layer &L = kLayers[5];
-        WgradArgs wa{n->h[4], n->gl, n->wpart, W, batch};
+        WgradArgs wa{n->h[4], n->gl, n->wpart, W, batch, L.dil};
         hipError_t e = launch_wgrad(64, 32, wa, nb, s);
         if (e == hipSuccess) e = launch_wgrad_reduce(n->wpart, nb, 64, 32, L.ci, L.co, n->g + L.off, s);
         if (e != hipSuccess) return e;
@@ -203,6 +208,7 @@ hipError_t backward(ge_nn_s *n, int batch, hipStream_t s)
         a.x = n->gl;
         a.w = n->wd[5];
         a.width = W;
+        a.dil = L.dil;
         a.res_in = nullptr;
         a.pre_in = n->pre[4];
         a.gh_out = n->gh;
@@ -213,7 +219,7 @@ hipError_t backward(ge_nn_s *n, int batch, hipStream_t s)
     int cur = 0;
     for (int l = 4; l >= 1; --l) {
         const Layer &L = kLayers[l];
-        WgradArgs wa{n->h[l - 1], n->gp[cur], n->wpart, W, batch};
+        WgradArgs wa{n->h[l - 1], n->gp[cur], n->wpart, W, batch, L.dil};
         hipError_t e = launch_wgrad(64, 64, wa, nb, s);
         if (e == hipSuccess) e = launch_wgrad_reduce(n->wpart, nb, 64, 64, L.ci, L.co, n->g + L.off, s);
         if (e != hipSuccess) return e;
@@ -221,6 +227,7 @@ hipError_t backward(ge_nn_s *n, int batch, hipStream_t s)
         a.x = n->gp[cur];
         a.w = n->wd[l];
         a.width = W;
+        a.dil = L.dil;
         a.res_in = n->gh;             // residual path of layer l (read and rewritten in place)
         a.pre_in = n->pre[l - 1];
         a.gh_out = n->gh;
@@ -230,7 +237,7 @@ hipError_t backward(ge_nn_s *n, int batch, hipStream_t s)
         cur = 1 - cur;
     }
     const Layer &L = kLayers[0];
-    WgradArgs wa{n->x, n->gp[cur], n->wpart, W, batch};
+    WgradArgs wa{n->x, n->gp[cur], n->wpart, W, batch, L.dil};
     hipError_t e = launch_wgrad(32, 64, wa, nb, s);
     if (e == hipSuccess) e = launch_wgrad_reduce(n->wpart, nb, 32, 64, L.ci, L.co, n->g + L.off, s);
     return e;

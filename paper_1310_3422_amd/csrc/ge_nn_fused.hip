@@ -3,12 +3,13 @@
 // activation in LDS, so HBM sees only u (read) and u_next (written) -- the
 // layer-by-layer path writes and re-reads 128 bytes per point per layer.
 //
-// Each layer is computed on kFR = kFP + 32 rows (16 beyond each side of the
-// tile).  A layer reads its input two rows either side, so after each layer
-// the rows whose inputs were not all computed grow by two at each edge of
-// the computed range; after six layers the valid rows still cover the tile
-// with four to spare.  Rows outside the rod are set to zero after every
-// layer, which is the zero padding of the layer-by-layer path.  The
+// Each layer is computed on kFR = kFP + 128 rows (64 beyond each side of the
+// tile).  A layer of tap spacing d reads its input 2d rows either side, so
+// after each layer the rows whose inputs were not all computed grow by 2d at
+// each edge of the computed range; after the six layers (spacings 1, 2, 4,
+// 8, 16, 1) that is 64 rows, and the valid rows are exactly the tile.  Rows
+// outside the rod are set to zero after every layer, which is the zero
+// padding of the layer-by-layer path.  The
 // arithmetic (the features, the MFMA accumulation order, the epilogues and
 // the jump) is the same expression sequence as the layer-by-layer kernels,
 // so both paths give the same bits.
@@ -25,17 +26,19 @@ namespace {
 
 using namespace dev;
 
-constexpr int kFP = 480;                   // output points per workgroup
-constexpr int kFHalo = 16;                 // computed rows beyond each side
-constexpr int kFR = kFP + 2 * kFHalo;      // rows computed per layer (32 M-tiles)
-constexpr int kFWaves = 4;                 // 8 M-tiles of 16 rows per wave
+constexpr int kFP = 512;                   // output points per workgroup
+constexpr int kFHalo = 64;                 // computed rows beyond each side (= 2 x sum of spacings)
+constexpr int kFR = kFP + 2 * kFHalo;      // rows computed per layer (40 M-tiles)
+constexpr int kFWaves = 4;                 // 10 M-tiles of 16 rows per wave
 constexpr int kFMT = kFR / 16 / kFWaves;
-constexpr int kFRows = kFR + 4;            // LDS rows: computed rows plus 2 each side
+constexpr int kFPad = 2 * kMaxDil;         // LDS rows beyond the computed rows on each side
+constexpr int kFRows = kFR + 2 * kFPad;
 constexpr int kFXS = 72;                   // LDS row pitch (bf16): 64 channels + 16 bytes
 constexpr int kFThreads = 64 * kFWaves;
 static_assert(kFR % (16 * kFWaves) == 0, "rows per wave");
 
-// LDS row i holds position w0 - kFHalo - 2 + i.
+// LDS row i holds position w0 - kFHalo - kFPad + i; computed row q is LDS
+// row q + kFPad.
 
 // Weights of one layer, packed [5][cout][cin] bf16, into LDS rows of kFXS.
 template <int CIN, int COUT>
@@ -51,7 +54,7 @@ __device__ __forceinline__ void load_weights(bf16 *ws, const bf16 *wt, int tid)
 // acc[m][n] += conv of the activations with the layer's weights for the
 // wave's M-tiles: same k-outer, channel-chunk-inner order as conv_kernel.
 template <int CIN, int COUT>
-__device__ __forceinline__ void layer_mfma(const bf16 *act, const bf16 *ws, int wv, int lane,
+__device__ __forceinline__ void layer_mfma(const bf16 *act, const bf16 *ws, int wv, int lane, int d,
                                            f32x4 (&acc)[kFMT][COUT / 16])
 {
     constexpr int NT = COUT / 16, KC = CIN / 32;
@@ -71,10 +74,10 @@ __device__ __forceinline__ void layer_mfma(const bf16 *act, const bf16 *ws, int 
                     &ws[(k * COUT + 16 * n + r16) * kFXS + 32 * c + 8 * g4]);
 #pragma unroll
             for (int m = 0; m < kFMT; ++m) {
-                // computed row q reads LDS rows q + k (q + 2 is its own row)
+                // computed row q reads LDS rows q + kFPad + (k - 2) d
                 const int q = 16 * (kFMT * wv + m) + r16;
-                const bf16x8 af =
-                    *reinterpret_cast<const bf16x8 *>(&act[(q + k) * kFXS + 32 * c + 8 * g4]);
+                const bf16x8 af = *reinterpret_cast<const bf16x8 *>(
+                    &act[(q + kFPad + (k - 2) * d) * kFXS + 32 * c + 8 * g4]);
 #pragma unroll
                 for (int n = 0; n < NT; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[n], acc[m][n],
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
 
     // features of every LDS row (zero outside the rod), channels 2..63 zero
     for (int i = tid; i < kFRows; i += kFThreads) {
-        const int w = w0 - kFHalo - 2 + i;
+        const int w = w0 - kFHalo - kFPad + i;
         bf16 *row = &act[i * kFXS];
         float f0 = 0.f, f1 = 0.f;
         if (w >= 0 && w < W) {
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
     // layers 1..5 (GELU; residual from layer 2 on)
     {
         f32x4 acc[kFMT][4];
-        layer_mfma<32, 64>(act, ws, wv, lane, acc);
+        layer_mfma<32, 64>(act, ws, wv, lane, a.dil[0], acc);
 #pragma unroll 1
         for (int l = 0; l < 5; ++l) {
             __syncthreads();   // every wave has finished reading act and ws
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
                         const int q = 16 * (kFMT * wv + m) + 4 * g4 + j;   // computed row
                         const int w = w0 - kFHalo + q;
                         const int ch = 16 * n + r16;
-                        bf16 *dst = &act[(q + 2) * kFXS + ch];
+                        bf16 *dst = &act[(q + kFPad) * kFXS + ch];
                         float v = acc[m][n][j] + bl[n];
                         float h = gelu(v);
                         if (l > 0) h += bf2f(*dst);
@@ -156,12 +159,12 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
             __syncthreads();   // activations and weights are in place
             if (tid < 64) bias[tid] = (l < 4) ? a.bias[l + 1][tid] : (tid < 16 ? a.bias[5][tid] : 0.f);
             __syncthreads();
-            if (l < 4) layer_mfma<64, 64>(act, ws, wv, lane, acc);
+            if (l < 4) layer_mfma<64, 64>(act, ws, wv, lane, a.dil[l + 1], acc);
         }
     }
     // layer 6 (64 -> 1, padded to 16 outputs) and the jump
     f32x4 acc6[kFMT][1];
-    layer_mfma<64, 16>(act, ws, wv, lane, acc6);
+    layer_mfma<64, 16>(act, ws, wv, lane, a.dil[5], acc6);
     if (r16 == 0) {
         const float b0 = bias[0];
         const float amp = 64.0f * rb * sc;
@@ -206,6 +209,12 @@ __global__ __launch_bounds__(256) void rod_scale_kernel(const float *u, int W, f
 
 hipError_t launch_jump_fused(const FusedArgs &a, int batch, hipStream_t s)
 {
+    int reach = 0;
+    for (int l = 0; l < 6; ++l) {
+        if (a.dil[l] < 1 || a.dil[l] > kMaxDil) return hipErrorInvalidValue;
+        reach += 2 * a.dil[l];
+    }
+    if (reach > kFHalo) return hipErrorInvalidValue;   // the tile would not stay valid
     hipLaunchKernelGGL(rod_scale_kernel, dim3(batch), dim3(256), 0, s, a.u, a.width, a.scale);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

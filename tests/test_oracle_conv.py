@@ -20,21 +20,35 @@ def test_conv_delta_response_reproduces_the_taps():
     assert np.count_nonzero(y[0, :3]) == 0 and np.count_nonzero(y[0, 8:]) == 0
 
 
+@pytest.mark.parametrize("d", [2, 5])
+def test_dilated_conv_delta_response(d):
+    rng = np.random.default_rng(d)
+    w = rng.standard_normal((5, 3, 2))
+    x = np.zeros((1, 41, 2))
+    x[0, 20, 0] = 1.0
+    y = cr.conv(x, w, d)
+    # y[p] = sum_k W[k] x[p + (k - 2) d]: the delta at 20 shows W[k] at p = 20 - (k - 2) d
+    for k in range(5):
+        np.testing.assert_array_equal(y[0, 20 - (k - 2) * d], w[k][:, 0])
+    assert np.count_nonzero(np.abs(y[0]).sum(axis=1)) == 5
+
+
 def test_conv_zero_padding_at_rod_ends():
     w = np.ones((5, 1, 1))
     x = np.ones((1, 6, 1))
     np.testing.assert_array_equal(cr.conv(x, w)[0, :, 0], [3, 4, 5, 5, 4, 3])
 
 
-def test_input_and_weight_gradients_are_adjoint():
+@pytest.mark.parametrize("d", [1, 3])
+def test_input_and_weight_gradients_are_adjoint(d):
     """<conv(x, w), g> = <x, conv_input_grad(g, w)> = <w, conv_weight_grad(x, g)>."""
     rng = np.random.default_rng(1)
     x = rng.standard_normal((2, 13, 4))
     w = rng.standard_normal((5, 3, 4))
     g = rng.standard_normal((2, 13, 3))
-    lhs = np.sum(cr.conv(x, w) * g)
-    assert lhs == pytest.approx(np.sum(x * cr.conv_input_grad(g, w)), rel=1e-12)
-    assert lhs == pytest.approx(np.sum(w * cr.conv_weight_grad(x, g)), rel=1e-12)
+    lhs = np.sum(cr.conv(x, w, d) * g)
+    assert lhs == pytest.approx(np.sum(x * cr.conv_input_grad(g, w, d)), rel=1e-12)
+    assert lhs == pytest.approx(np.sum(w * cr.conv_weight_grad(x, g, d)), rel=1e-12)
 
 
 def test_gelu_values():
@@ -57,8 +71,8 @@ def _small_params(seed):
 def test_backward_matches_central_differences():
     rng = np.random.default_rng(2)
     params = _small_params(3)
-    x = rng.standard_normal((2, 9, 2))
-    t = rng.standard_normal((2, 9))
+    x = rng.standard_normal((2, 37, 2))
+    t = rng.standard_normal((2, 37))
     loss, grads = cr.loss_and_grads(params, x, t)
     eps = 1e-5   # central-difference truncation ~eps^2, roundoff ~1e-16/eps
     for li in range(len(params)):
@@ -90,6 +104,19 @@ def test_bf16_rounding_values():
     assert out[3] == -2.5
     assert out[4] == 3.140625
     assert out[5] == np.float64(np.float32(1e-40)).item() or abs(out[5]) < 1e-38
+
+
+def test_receptive_field_is_64_points():
+    """A change of the input at one point reaches the output exactly
+    2 (1 + 2 + 4 + 8 + 16 + 1) = 64 points away and no farther (all weights
+    nonzero, so no tap is hidden)."""
+    params = [(np.ones((5, co, ci)) * 0.1, np.zeros(co)) for ci, co in cr.LAYERS]
+    x = np.zeros((1, 201, 2))
+    base, _ = cr.forward(params, x)
+    x[0, 100, 0] = 1.0
+    out, _ = cr.forward(params, x)
+    reach = np.nonzero(np.abs(out - base)[0] > 0)[0]
+    assert reach.min() == 100 - 64 and reach.max() == 100 + 64
 
 
 def test_parameter_count():

@@ -267,15 +267,17 @@ def main():
     peak_tf = VALU_LANE_OPS_BY_PREC[prec] * FLOPS_PER_UPDATE[prec] / VALU_PER_UPDATE[prec] / 1e12
     achieved_tf = flops / kernel_s / 1e12
     hbm_bytes = 2 * BYTES_PER_POINT[prec] * n      # one read + one write per launch
-    tkey = f"{prec}_n{n}_k{cfg['tile']}_w{cfg['waves']}_d{cfg['depth']}"
+    tkey = f"{prec}_n{n}_k{cfg['tile']}_w{cfg['waves']}_d{cfg['depth']}_s{cfg['schedule']}"
     roofline = {
         "bound": "alu", "achieved": round(achieved_tf, 3), "peak": round(peak_tf, 2),
         "unit": "TFLOP/s", "frac": round(achieved_tf / peak_tf, 4),
         "traffic": recorded_traffic(tkey),
         "peak_basis": f"VALU issue {VALU_LANE_OPS_BY_PREC[prec]:.3g} lane-ops/s x {FLOPS_PER_UPDATE[prec]} "
                       f"flops / {VALU_PER_UPDATE[prec]} VALU ops per update",
-        "kernel": f"tile_kernel<{'double' if prec == 'fp64' else 'float'},{cfg['tile']},"
-                  f"{cfg['waves']},{'comp' if prec == 'fp32c' else 'plain'}>",
+        "kernel": (f"tile_persistent_kernel<{'double' if prec == 'fp64' else 'float'},{cfg['tile']},"
+                   f"{'comp' if prec == 'fp32c' else 'plain'}>" if cfg["schedule"] == 2 else
+                   f"tile_kernel<{'double' if prec == 'fp64' else 'float'},{cfg['tile']},"
+                   f"{cfg['waves']},{'comp' if prec == 'fp32c' else 'plain'}>"),
         "depth": cfg["depth"], "launches": nl, "avg_launch_us": round(kernel_s * 1e6, 2),
         "algorithmic_flops_per_launch": flops,
         "hbm_gbs_algorithmic": round(hbm_bytes / kernel_s / 1e9, 1),

@@ -149,15 +149,15 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
     const int prec = d->precision;
     int tile = d->tile, waves = d->waves, depth = d->depth;
     // Defaults measured on MI355X on a rod of 2^24 points: FP64 runs best
-    // with 16 points per lane, one wave per workgroup and 48 levels per
-    // launch; both FP32 forms with four waves (4096-point windows) and 128
-    // levels.  A depth left at 0 is clipped so that the halo stays within a
-    // quarter of the window.
+    // with 32 points per lane, one wave per workgroup, 96 levels per launch
+    // and the persistent schedule; both FP32 forms with 16 points per lane,
+    // four waves (4096-point windows) and 128 levels.  A depth left at 0 is
+    // clipped so that the halo stays within a quarter of the window.
     const bool wide = prec != ge::kFP64;
-    if (tile == 0) tile = 16;
+    if (tile == 0) tile = wide ? 16 : 32;
     if (waves == 0) waves = wide ? 4 : 1;
     if (depth == 0) {
-        depth = wide ? 128 : 48;
+        depth = wide ? 128 : 96;
         const int al = (prec == ge::kFP64) ? 2 : 4;
         while (depth > 1 && 4 * round_up(depth + 1, al) > (int64_t)waves * 64 * tile) --depth;
     }
@@ -206,7 +206,11 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
         }
         p->ntiles = (p->n + p->core - 1) / p->core;
     }
-    p->persistent = !p->single && p->ntiles >= 3 && d->schedule == 2;
+    // the library's choice: persistent wherever it is built and the rod has
+    // enough tiles for the prefetch to matter
+    const bool auto_persistent = d->schedule == 0 && waves == 1 && prec == ge::kFP64 &&
+                                 ge::persistent_supported(prec, tile) && p->ntiles >= 64;
+    p->persistent = !p->single && p->ntiles >= 3 && (d->schedule == 2 || auto_persistent);
     const double r = p->r;
     p->h = 1.0 / (double)(p->n + 1);
     p->tau = r * p->h * p->h;

@@ -47,6 +47,10 @@ FLOPS_PER_UPDATE = {"fp64": 6, "fp32": 6, "fp32c": 12}
 VALU_PER_UPDATE = {"fp64": 4, "fp32": 5, "fp32c": 11}
 BYTES_PER_POINT = {"fp64": 8, "fp32": 4, "fp32c": 8}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "tile_sweep_traffic.md")
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak, published
+# surrogate: algorithmic flops per point of one 64-level jump (real channels:
+# 2->64, four 64->64, 64->1, five taps, multiply-add = 2)
+NN_FLOPS_PER_POINT = 2 * 5 * (2 * 64 + 4 * 64 * 64 + 64 * 1)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1310_3422_amd", "csrc", f)
                   for f in ("ge_sweep.hip", "ge_level.h", "ge_kernels.h")]
 
@@ -129,7 +133,9 @@ def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
     from paper_1310_3422_amd import ge, surrogate, inputs
     t0 = time.perf_counter()
     net = ge.Net(width=width, max_batch=nrods, seed=4)
-    tr = surrogate.Trainer(net, seed=4, ntraj=4096, chunk=1024, njumps=8, minibatch=64)
+    tr = surrogate.Trainer(net, seed=4, ntraj=4096, chunk=1024, njumps=8, minibatch=64,
+                           noise=surrogate.TRAIN_NOISE, modes=surrogate.TRAIN_MODES)
+    torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     log = tr.train(train_steps, lr=2e-3, lr_final=5e-5, log_every=max(train_steps // 8, 1))
@@ -137,15 +143,20 @@ def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
     train_s = time.perf_counter() - t0
     res = surrogate.evaluate(net, seed=41, nrods=512, width=width)
     med = {k: {m: float(np.median(v[m])) for m in v} for k, v in res.items()}
+    roll = surrogate.rollout(net, seed=41, nrods=256, width=width, njumps=8)
     # timing at a batch of nrods rods
     r, u0 = inputs.surrogate_rods(42, nrods, n=width)
     rf = torch.from_numpy(r.astype(np.float32)).cuda()
     u32 = torch.from_numpy(u0.astype(np.float32).ravel()).cuda()
     r64 = r.astype(np.float32).astype(np.float64)
+    fwd_flops = NN_FLOPS_PER_POINT * width                 # algorithmic, one rod-jump
+    train_tf = 3 * fwd_flops * 64 * train_steps / train_s / 1e12
     out = {"train_steps": train_steps, "train_minibatch": 64, "trajectories": 4096,
            "data_gen_s": round(gen_s, 2), "train_s": round(train_s, 2),
-           "loss_log": log, "median_rel_l2_vs_ge64": med, "batch_rods": nrods,
-           "width": width}
+           "train_tflops_algorithmic": round(train_tf, 1),
+           "loss_log": log, "median_rel_l2_vs_ge64": med,
+           "rollout_median_rel_l2_per_jump": [float(np.median(x)) for x in roll],
+           "batch_rods": nrods, "width": width}
     times = {}
     plan64 = surrogate.fp64_batch(r64, width)
     ws64 = plan64.new_workspace()
@@ -192,6 +203,11 @@ def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
                       "rod_windows": nrods * njumps // 8, "fallback_rod_windows": nfb,
                       "median_last_rel_l2": float(err.median().cpu())}
     out["us_per_rod_jump"] = {k: round(v / nrods * 1e6, 4) for k, v in times.items()}
+    ach = fwd_flops * nrods / times["surrogate_jump"] / 1e12
+    out["roofline_fused_jump"] = {"bound": "mfma", "achieved": round(ach, 1),
+                                  "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": round(ach / BF16_PEAK_TFLOPS, 4),
+                                  "flops_per_rod_jump": fwd_flops}
     out["speedup_vs_ge64_fp64"] = {k: round(times["ge64_fp64"] / v, 3) for k, v in times.items()}
     return out
 
@@ -354,8 +370,12 @@ def main():
             wb, gb = time_runs(torch, stream,
                                lambda: bt.solve(ub, 0, 2000, wsb, stream=stream), 1, 3)
         info = bt.info()
+        bups = float(rb.n.sum()) * 2000 * 3 / gb
+        bpeak = VALU_LANE_OPS_BY_PREC["fp32"] * FLOPS_PER_UPDATE["fp32"] / VALU_PER_UPDATE["fp32"] / 1e12
         extra["rod_batch_4096_fp32"] = {
-            "updates_per_s": float(rb.n.sum()) * 2000 * 3 / gb,
+            "roofline": {"bound": "alu", "achieved": round(bups * 6 / 1e12, 2), "peak": round(bpeak, 1),
+                         "unit": "TFLOP/s", "frac": round(bups * 6 / 1e12 / bpeak, 4)},
+            "updates_per_s": bups,
             "ms_per_run": gb / 3 * 1e3, "tasks": info["ntasks"], "workgroups": info["grid"],
             "rods": rb.nrods, "points": int(rb.n.sum()), "levels": 2000}
         del ub, wsb, bt

@@ -107,6 +107,24 @@ class Trainer:
         return out
 
 
+# Training data of the bundled recipe: rods whose spectrum runs from 16 up to
+# a log-uniform cutoff in [16, 512] modes, plus white noise of relative size
+# log-uniform in [1e-9, 1e-5], so that the network sees, and learns how the
+# sweep damps, every wavelength it may meet when jumps are chained.
+TRAIN_MODES = (16, 512)
+TRAIN_NOISE = (1e-9, 1e-5)
+
+
+def train_recipe(net, steps, seed=4, ntraj=4096, minibatch=64, lr=2e-3, lr_final=5e-5,
+                 log_every=0):
+    """Generate the recipe's trajectories with the batch sweep and train
+    ``steps`` Adam steps; returns (trainer, loss log)."""
+    tr = Trainer(net, seed=seed, ntraj=ntraj, chunk=min(1024, ntraj), njumps=8,
+                 minibatch=minibatch, noise=TRAIN_NOISE, modes=TRAIN_MODES)
+    log = tr.train(steps, lr=lr, lr_final=lr_final, log_every=log_every)
+    return tr, log
+
+
 def rel_l2_rows(x, y):
     """Per-row ||x - y|| / ||y|| of two (rods, width) arrays, in FP64."""
     x = np.asarray(x, dtype=np.float64)

@@ -221,7 +221,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
-    ap.add_argument("--surrogate-steps", type=int, default=3000,
+    ap.add_argument("--surrogate-steps", type=int, default=24000,
                     help="training steps of the surrogate extra (0: skip it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a 1 GiB fill and a 1 GiB streaming read+write (counter "

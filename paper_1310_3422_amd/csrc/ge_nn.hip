@@ -103,39 +103,60 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a)
             for (int m = 0; m < 2; ++m)
 #pragma unroll
                 for (int n = 0; n < NT; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bfr[n], acc[m][n],
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[n], af[m], acc[m][n],
                                                                        0, 0, 0);
         }
     }
 
-    // epilogue: lane holds D[row = 4*g4 + j][col = r16] of each 16x16 tile
+    // epilogue: the product is taken transposed (weights as the A operand),
+    // so lane holds channels 16 n + 4 (lane / 16) + j of position
+    // 32 wv + 16 m + lane % 16, four consecutive channels: one 8-byte access
     const int64_t rowbase = (int64_t)b * W;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
+        const int pl = 32 * wv + 16 * m + r16;              // position within the tile
+        const int w = w0 + pl;
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
+            const int ch0 = 16 * n + 4 * g4;
+            const int64_t o = (rowbase + w) * COUT + ch0;
+            float v[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int pl = 32 * wv + 16 * m + 4 * g4 + j;   // position within the tile
-                const int w = w0 + pl;
-                const int ch = 16 * n + r16;
-                float v = acc[m][n][j];
-                if (a.bias) v += a.bias[ch];
-                const int64_t o = (rowbase + w) * COUT + ch;
-                if constexpr (EPI == kEpiGelu || EPI == kEpiGeluRes) {
-                    if (a.pre_out) static_cast<bf16 *>(a.pre_out)[o] = f2bf(v);
-                    float act = gelu(v);
-                    if constexpr (EPI == kEpiGeluRes) act += bf2f(xs[(pl + 2 * d) * XS + ch]);
-                    static_cast<bf16 *>(a.act_out)[o] = f2bf(act);
-                } else if constexpr (EPI == kEpiOut) {
-                    if (ch == 0) a.out_f32[rowbase + w] = v;
-                } else {   // kEpiBwd
-                    if (a.res_in) v += bf2f(static_cast<const bf16 *>(a.res_in)[o]);
-                    const bf16 gh = f2bf(v);
-                    if (a.gh_out) static_cast<bf16 *>(a.gh_out)[o] = gh;
-                    const float pre = bf2f(static_cast<const bf16 *>(a.pre_in)[o]);
-                    static_cast<bf16 *>(a.gp_out)[o] = f2bf(bf2f(gh) * gelu_grad(pre));
+                v[j] = acc[m][n][j];
+                if (a.bias) v[j] += a.bias[ch0 + j];
+            }
+            if constexpr (EPI == kEpiGelu || EPI == kEpiGeluRes) {
+                bf16x4 pre, act, xres;
+                if constexpr (EPI == kEpiGeluRes)
+                    xres = *reinterpret_cast<const bf16x4 *>(&xs[(pl + 2 * d) * XS + ch0]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    pre[j] = f2bf(v[j]);
+                    float h = gelu(v[j]);
+                    if constexpr (EPI == kEpiGeluRes) h += bf2f(xres[j]);
+                    act[j] = f2bf(h);
                 }
+                if (a.pre_out) *reinterpret_cast<bf16x4 *>(&static_cast<bf16 *>(a.pre_out)[o]) = pre;
+                *reinterpret_cast<bf16x4 *>(&static_cast<bf16 *>(a.act_out)[o]) = act;
+            } else if constexpr (EPI == kEpiOut) {
+                if (ch0 == 0) a.out_f32[rowbase + w] = v[0];
+            } else {   // kEpiBwd
+                bf16x4 gh, gp;
+                const bf16x4 pre = *reinterpret_cast<const bf16x4 *>(
+                    &static_cast<const bf16 *>(a.pre_in)[o]);
+                bf16x4 res;
+                if (a.res_in)
+                    res = *reinterpret_cast<const bf16x4 *>(&static_cast<const bf16 *>(a.res_in)[o]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float g = v[j];
+                    if (a.res_in) g += bf2f(res[j]);
+                    gh[j] = f2bf(g);
+                    gp[j] = f2bf(bf2f(gh[j]) * gelu_grad(bf2f(pre[j])));
+                }
+                if (a.gh_out) *reinterpret_cast<bf16x4 *>(&static_cast<bf16 *>(a.gh_out)[o]) = gh;
+                *reinterpret_cast<bf16x4 *>(&static_cast<bf16 *>(a.gp_out)[o]) = gp;
             }
         }
     }

@@ -53,6 +53,10 @@ __device__ __forceinline__ void load_weights(bf16 *ws, const bf16 *wt, int tid)
 
 // acc[m][n] += conv of the activations with the layer's weights for the
 // wave's M-tiles: same k-outer, channel-chunk-inner order as conv_kernel.
+// The product is taken transposed (weights as the A operand, activations
+// as B), so that each lane ends with four consecutive output channels of one
+// position: acc[m][n][j] is channel 16 n + 4 (lane / 16) + j of position
+// 16 (M-tile) + lane % 16, which the epilogue stores as one 8-byte word.
 template <int CIN, int COUT>
 __device__ __forceinline__ void layer_mfma(const bf16 *act, const bf16 *ws, int wv, int lane, int d,
                                            f32x4 (&acc)[kFMT][COUT / 16])
@@ -80,7 +84,7 @@ __device__ __forceinline__ void layer_mfma(const bf16 *act, const bf16 *ws, int 
                     &act[(q + kFPad + (k - 2) * d) * kFXS + 32 * c + 8 * g4]);
 #pragma unroll
                 for (int n = 0; n < NT; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[n], acc[m][n],
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[n], af, acc[m][n],
                                                                        0, 0, 0);
             }
         }
@@ -131,9 +135,11 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
 #pragma unroll 1
         for (int l = 0; l < 5; ++l) {
             __syncthreads();   // every wave has finished reading act and ws
-            float bl[4];
+            float bl[4][4];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) bl[n] = bias[16 * n + r16];
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bl[n][j] = bias[16 * n + 4 * g4 + j];
             // the next layer's weights load while the epilogue runs
             if (l < 4)
                 load_weights<64, 64>(ws, static_cast<const bf16 *>(a.w[l + 1]), tid);
@@ -141,19 +147,22 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
                 load_weights<64, 16>(ws, static_cast<const bf16 *>(a.w[5]), tid);
 #pragma unroll
             for (int m = 0; m < kFMT; ++m) {
+                const int q = 16 * (kFMT * wv + m) + r16;          // computed row (position)
+                const int w = w0 - kFHalo + q;
+                const bool in = w >= 0 && w < W;
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
+                    bf16x4 *dst = reinterpret_cast<bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]);
+                    bf16x4 hv;
+                    if (l > 0) hv = *dst;
+                    bf16x4 o;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int q = 16 * (kFMT * wv + m) + 4 * g4 + j;   // computed row
-                        const int w = w0 - kFHalo + q;
-                        const int ch = 16 * n + r16;
-                        bf16 *dst = &act[(q + kFPad) * kFXS + ch];
-                        float v = acc[m][n][j] + bl[n];
-                        float h = gelu(v);
-                        if (l > 0) h += bf2f(*dst);
-                        *dst = (w >= 0 && w < W) ? f2bf(h) : f2bf(0.f);
+                        float h = gelu(acc[m][n][j] + bl[n][j]);
+                        if (l > 0) h += bf2f(hv[j]);
+                        o[j] = in ? f2bf(h) : f2bf(0.f);
                     }
+                    *dst = o;
                 }
             }
             __syncthreads();   // activations and weights are in place
@@ -165,21 +174,20 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
     // layer 6 (64 -> 1, padded to 16 outputs) and the jump
     f32x4 acc6[kFMT][1];
     layer_mfma<64, 16>(act, ws, wv, lane, a.dil[5], acc6);
-    if (r16 == 0) {
+    if (g4 == 0) {
+        // channel 0 of position 16 (M-tile) + r16
         const float b0 = bias[0];
         const float amp = 64.0f * rb * sc;
 #pragma unroll
-        for (int m = 0; m < kFMT; ++m)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int q = 16 * (kFMT * wv + m) + 4 * g4 + j;
-                const int p = q - kFHalo;                       // point within the tile
-                const int w = w0 + p;
-                if (p >= 0 && p < kFP && w < W) {
-                    const float out = acc6[m][0][j] + b0;
-                    a.u_next[base + w] = ub[w] + amp * out;
-                }
+        for (int m = 0; m < kFMT; ++m) {
+            const int q = 16 * (kFMT * wv + m) + r16;
+            const int p = q - kFHalo;                       // point within the tile
+            const int w = w0 + p;
+            if (p >= 0 && p < kFP && w < W) {
+                const float out = acc6[m][0][0] + b0;
+                a.u_next[base + w] = ub[w] + amp * out;
             }
+        }
     }
 }
 

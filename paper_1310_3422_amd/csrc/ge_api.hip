@@ -154,6 +154,12 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
     // four waves (4096-point windows) and 128 levels.  A depth left at 0 is
     // clipped so that the halo stays within a quarter of the window.
     const bool wide = prec != ge::kFP64;
+    if (depth == 1) {
+        // one level per launch is a pure stream: small tiles (one 16-byte
+        // chunk per lane) and single-wave workgroups move the most bytes
+        if (tile == 0) tile = wide ? 4 : 2;
+        if (waves == 0) waves = 1;
+    }
     if (tile == 0) tile = wide ? 16 : 32;
     if (waves == 0) waves = wide ? 4 : 1;
     if (depth == 0) {

@@ -198,3 +198,52 @@ def advance_with_recheck(net, u, r, njumps, ge_batch=None, r64=None, check=8, to
     nfb = net.advance(ge_batch, ws, u, r, njumps, step0=step0, check=check, tol=tol,
                       accepted=acc, fallbacks=fb, last_err=err, stream=stream)
     return nfb, acc.cpu().numpy(), fb.cpu().numpy(), err.cpu().numpy()
+
+
+# algorithmic flops of one 64-level jump per point (real channels 2->64,
+# four 64->64, 64->1; five taps; multiply-add counted as 2)
+FLOPS_PER_POINT = 2 * 5 * (2 * 64 + 4 * 64 * 64 + 64 * 1)
+
+
+def time_jump(batch=1024, width=4096, reps=5, seed=42):
+    """Time the fused jump (an untrained network: the arithmetic does not
+    depend on the weights) on ``batch`` seeded rods; returns a dict."""
+    torch = _torch()
+    net = ge.Net(width=width, max_batch=batch, seed=4)
+    r, u0 = inputs.surrogate_rods(seed, batch, n=width)
+    u = torch.from_numpy(u0.astype(np.float32).ravel()).cuda()
+    rf = torch.from_numpy(r.astype(np.float32)).cuda()
+    out = torch.empty_like(u)
+    for _ in range(2):
+        net.jump(u, rf, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.jump(u, rf, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"batch": batch, "width": width, "ms_per_jump": ms,
+            "tflops_algorithmic": FLOPS_PER_POINT * width * batch / ms / 1e9}
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="surrogate utilities")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    tj = sub.add_parser("time-jump", help="time the fused 64-level jump")
+    tj.add_argument("--batch", type=int, default=1024)
+    tj.add_argument("--width", type=int, default=4096)
+    tj.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    if args.cmd == "time-jump":
+        print(json.dumps(time_jump(args.batch, args.width, args.reps)), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main())

@@ -133,14 +133,10 @@ def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
     from paper_1310_3422_amd import ge, surrogate, inputs
     t0 = time.perf_counter()
     net = ge.Net(width=width, max_batch=nrods, seed=4)
-    tr = surrogate.Trainer(net, seed=4, ntraj=4096, chunk=1024, njumps=8, minibatch=64,
-                           noise=surrogate.TRAIN_NOISE, modes=surrogate.TRAIN_MODES)
+    tr, log = surrogate.train_recipe(net, train_steps, seed=4, ntraj=4096, minibatch=64,
+                                     log_every=max(train_steps // 8, 1))
     torch.cuda.synchronize()
-    gen_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    log = tr.train(train_steps, lr=2e-3, lr_final=5e-5, log_every=max(train_steps // 8, 1))
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
+    train_s = time.perf_counter() - t0      # trajectory generation included
     res = surrogate.evaluate(net, seed=41, nrods=512, width=width)
     med = {k: {m: float(np.median(v[m])) for m in v} for k, v in res.items()}
     roll = surrogate.rollout(net, seed=41, nrods=256, width=width, njumps=8)
@@ -152,7 +148,7 @@ def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
     fwd_flops = NN_FLOPS_PER_POINT * width                 # algorithmic, one rod-jump
     train_tf = 3 * fwd_flops * 64 * train_steps / train_s / 1e12
     out = {"train_steps": train_steps, "train_minibatch": 64, "trajectories": 4096,
-           "data_gen_s": round(gen_s, 2), "train_s": round(train_s, 2),
+           "train_s": round(train_s, 2),
            "train_tflops_algorithmic": round(train_tf, 1),
            "loss_log": log, "median_rel_l2_vs_ge64": med,
            "rollout_median_rel_l2_per_jump": [float(np.median(x)) for x in roll],

@@ -58,9 +58,38 @@ class Trajectories:
         return self.states[j].view(self.nrods, self.width)
 
 
+class SelfRollout:
+    """Pairs (v, 64 GE levels from v) where v is the network's own state after
+    ``jumps`` jumps from a random state of each rod of a trajectory chunk:
+    training on them teaches the network to correct the errors its chained
+    jumps accumulate.  Shaped like a one-jump Trajectories."""
+
+    def __init__(self, net, traj, jumps, rng):
+        torch = _torch()
+        W, nr = net.width, traj.nrods
+        self.nrods, self.njumps, self.width, self.r = nr, 1, W, traj.r
+        j0 = torch.from_numpy(rng.integers(0, traj.njumps, nr)).cuda()
+        st = traj.states.view(traj.njumps + 1, nr, W)
+        u = st[j0, torch.arange(nr, device="cuda")].reshape(-1).contiguous()
+        nxt = torch.empty_like(u)
+        for _ in range(jumps):
+            for i in range(0, nr, net.max_batch):
+                b = min(net.max_batch, nr - i)
+                sl = slice(i * W, (i + b) * W)
+                net.jump(u[sl], traj.r[i:i + b].contiguous(), out=nxt[sl])
+            u, nxt = nxt, u
+        self.states = torch.empty((2, nr * W), dtype=torch.float32, device="cuda")
+        self.states[0].copy_(u)
+        g = ge.f32_to_f64(u)
+        traj.plan.solve(g, 0, JUMP, traj.plan.new_workspace())
+        ge.f64_to_f32(g, out=self.states[1])
+
+
 class Trainer:
     """Adam on minibatches of (u, u after 64 levels) pairs drawn from
-    trajectory chunks; chunk c of a data set with seed s uses seed [s, c]."""
+    trajectory chunks; chunk c of a data set with seed s uses seed [s, c].
+    Optionally, self-rollout pair sets (SelfRollout) are refreshed during
+    training and sampled for a share of the minibatches."""
 
     def __init__(self, net, seed=4, ntraj=2048, chunk=1024, njumps=8, minibatch=64,
                  noise=None, modes=None):
@@ -80,10 +109,25 @@ class Trainer:
         self.r = torch.empty(B, dtype=torch.float32, device="cuda")
         self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
         self.steps = 0
+        self.selfsets = []
+        self.self_share = 0.0
+        self.nself = 0
+
+    def refresh_self(self, max_jumps=7, keep=4):
+        """Add a self-rollout pair set (jumps cycling 1..max_jumps) from a
+        random chunk, keeping the newest ``keep``."""
+        c = self.chunks[int(self.rng.integers(len(self.chunks)))]
+        jumps = 1 + self.nself % max_jumps
+        self.nself += 1
+        self.selfsets.append(SelfRollout(self.net, c, jumps, self.rng))
+        del self.selfsets[:-keep]
 
     def _gather(self):
         torch = _torch()
-        c = self.chunks[int(self.rng.integers(len(self.chunks)))]
+        if self.selfsets and self.rng.random() < self.self_share:
+            c = self.selfsets[int(self.rng.integers(len(self.selfsets)))]
+        else:
+            c = self.chunks[int(self.rng.integers(len(self.chunks)))]
         rods = torch.from_numpy(self.rng.integers(0, c.nrods, self.minibatch)).cuda()
         js = torch.from_numpy(self.rng.integers(0, c.njumps, self.minibatch)).cuda()
         W = self.net.width
@@ -92,12 +136,19 @@ class Trainer:
         self.u64.view(-1, W).copy_(st[js + 1, rods])
         self.r.copy_(c.r[rods])
 
-    def train(self, steps, lr=1e-3, lr_final=None, log_every=0):
+    def train(self, steps, lr=1e-3, lr_final=None, log_every=0, self_start=None, self_every=0,
+              self_share=0.5):
         """``steps`` Adam steps with the rate decaying geometrically from lr to
-        lr_final; returns the losses at the logged steps."""
+        lr_final; from step ``self_start`` on, a self-rollout set is added
+        every ``self_every`` steps and drawn for a ``self_share`` of the
+        minibatches.  Returns the losses at the logged steps."""
         lr_final = lr if lr_final is None else lr_final
         out = []
         for i in range(steps):
+            if self_every and self_start is not None and i >= self_start and \
+                    (i - self_start) % self_every == 0:
+                self.refresh_self()
+                self.self_share = self_share
             rate = lr * (lr_final / lr) ** (i / max(steps - 1, 1))
             self._gather()
             self.net.train_step(self.u, self.u64, self.r, rate, loss=self.loss)
@@ -118,10 +169,12 @@ TRAIN_NOISE = (1e-9, 1e-5)
 def train_recipe(net, steps, seed=4, ntraj=4096, minibatch=64, lr=2e-3, lr_final=5e-5,
                  log_every=0):
     """Generate the recipe's trajectories with the batch sweep and train
-    ``steps`` Adam steps; returns (trainer, loss log)."""
+    ``steps`` Adam steps, the second half with self-rollout sets refreshed
+    12 times and drawn for half the minibatches; returns (trainer, loss log)."""
     tr = Trainer(net, seed=seed, ntraj=ntraj, chunk=min(1024, ntraj), njumps=8,
                  minibatch=minibatch, noise=TRAIN_NOISE, modes=TRAIN_MODES)
-    log = tr.train(steps, lr=lr, lr_final=lr_final, log_every=log_every)
+    log = tr.train(steps, lr=lr, lr_final=lr_final, log_every=log_every,
+                   self_start=steps // 2, self_every=max(steps // 24, 1), self_share=0.5)
     return tr, log
 
 

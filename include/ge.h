@@ -183,6 +183,10 @@ typedef struct {
                              /* store it (file $GE_TUNE_CACHE, default        */
                              /* ~/.cache/libge/batch_tune.txt); 0: use the    */
                              /* stored measurement, or built-in defaults      */
+    int32_t sync;            /* how the waves of a rod meet every level:      */
+                             /* 0 = library choice, 1 = workgroup barrier,    */
+                             /* 2 = each wave waits for its two neighbours    */
+                             /* only (level flags in LDS)                     */
 } ge_batch_desc;
 
 /* Create a batch plan: choose points per lane for every rod, bundle rods

@@ -34,6 +34,8 @@ struct BatchArgs {
     int64_t step0;
     int32_t nsteps;
     int32_t ntasks;
+    int32_t sync;             // 1: workgroup barrier per level; 2: neighbour flags
+    int32_t pad;
 };
 
 hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream);

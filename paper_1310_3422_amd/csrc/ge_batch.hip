@@ -35,10 +35,27 @@ using namespace dev;
 constexpr int kWaves = kBatchWaves;          // waves per workgroup
 constexpr int kThreads = kWaves * kWave;
 
-template <typename T, int K, bool COMP, bool WALL>
+// Wait until a neighbouring wave has published the edges of the level this
+// wave is on.  Every wave publishes before it waits, so a wait on level i
+// ends once the neighbour has finished level i - 1 (a few microseconds); the
+// bound of 65536 polls (milliseconds) only keeps a wave from spinning forever
+// should that ever fail.
+__device__ __forceinline__ void wait_level(const int *flag, int tag)
+{
+    int n = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < tag) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++n > (1 << 16)) break;
+    }
+}
+
+// NBR: the waves of a rod synchronise with their neighbours only (per-wave
+// level flags in LDS) instead of the whole workgroup meeting at a barrier
+// every level; hasR: the next wave holds the rest of this rod.
+template <typename T, int K, bool COMP, bool WALL, bool NBR>
 __device__ __forceinline__ void rod_levels(const BatchArgs &a, const BatchRod &rd, int wr,
-                                           T (&s)[K], T (&e)[K], T (*xs)[kWaves][4],
-                                           T (*xe)[kWaves][4])
+                                           bool hasR, T (&s)[K], T (&e)[K],
+                                           T (*xs)[kWaves][4], T (*xe)[kWaves][4], int *lvl)
 {
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     // the wave index is uniform across the wave: let the compiler keep
@@ -76,7 +93,17 @@ __device__ __forceinline__ void rod_levels(const BatchArgs &a, const BatchRod &r
             if (lane == 0) { xe[pb][w][0] = e[0]; xe[pb][w][1] = e[1]; }
             if (lane == kWave - 1) { xe[pb][w][2] = e[K - 2]; xe[pb][w][3] = e[K - 1]; }
         }
-        __syncthreads();
+        if constexpr (NBR) {
+            // publish this level's edges (the release orders the writes
+            // above before the flag), then wait for the neighbours' edges
+            const int tag = lev + 1;   // lev counts this call's levels from 0
+            if (lane == 0)
+                __hip_atomic_store(&lvl[w], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (wr > 0) wait_level(&lvl[w - 1], tag);
+            if (hasR) wait_level(&lvl[w + 1], tag);
+        } else {
+            __syncthreads();
+        }
         const int wl = w > 0 ? w - 1 : 0, wrr = w < kWaves - 1 ? w + 1 : kWaves - 1;
         T xl = xs[pb][wl][3], xr = xs[pb][wrr][0], xl2 = xs[pb][wl][2], xr2 = xs[pb][wrr][1];
         T yl = T(0), yr = T(0), yl2 = T(0), yr2 = T(0);
@@ -104,9 +131,10 @@ __device__ __forceinline__ void rod_levels(const BatchArgs &a, const BatchRod &r
     });
 }
 
-// Every wave of the workgroup executes the same number of barriers: waves
-// without a rod in this task run the level loop on dummy data.
-template <typename T, int K, bool COMP>
+// Barrier mode: every wave of the workgroup executes the same number of
+// barriers, so waves without a rod in this task run the level loop on dummy
+// data.  Neighbour mode: such waves skip the loop.
+template <typename T, int K, bool COMP, bool NBR>
 __device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk)
 {
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
@@ -115,8 +143,14 @@ __device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
     __shared__ T xs[2][kWaves][4];
     __shared__ T xe[2][kWaves][4];
+    __shared__ int lvl[kWaves];
     const int rod = tk.wave_rod[w];
     const int wr = tk.wave_idx[w];
+    const bool hasR = rod >= 0 && w + 1 < kWaves && tk.wave_rod[w + 1] == rod;
+    if constexpr (NBR) {
+        if (lane == 0) lvl[w] = 0;
+        __syncthreads();   // every flag reset before any wave publishes
+    }
     T s[K], e[K];
     BatchRod rd{};
     T *us = nullptr, *ue = nullptr;
@@ -140,10 +174,12 @@ __device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk
     }
     const int64_t w0 = (int64_t)wr * kWave * K;
     const bool wall = (rod >= 0) && (wr == 0 || rd.n - w0 <= (int64_t)kWave * K);
-    if (wall)
-        rod_levels<T, K, COMP, true>(a, rd, wr, s, e, xs, xe);
-    else
-        rod_levels<T, K, COMP, false>(a, rd, wr, s, e, xs, xe);
+    if (!NBR || rod >= 0) {
+        if (wall)
+            rod_levels<T, K, COMP, true, NBR>(a, rd, wr, hasR, s, e, xs, xe, lvl);
+        else
+            rod_levels<T, K, COMP, false, NBR>(a, rd, wr, hasR, s, e, xs, xe, lvl);
+    }
     if (rod >= 0) {
         store_lane_upto<T, K>(us + g0, g0, rd.n, s);
         if constexpr (COMP) store_lane_upto<T, K>(ue + g0, g0, rd.n, e);
@@ -151,7 +187,7 @@ __device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk
     __syncthreads();   // LDS slots are reused by the next task
 }
 
-template <typename T, bool COMP>
+template <typename T, bool COMP, bool NBR>
 __global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
 {
     __shared__ int task_s;
@@ -165,12 +201,12 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
             break;
         const BatchTask &tk = a.tasks[task];
         switch (tk.k) {
-        case 4: run_task<T, 4, COMP>(a, tk); break;
-        case 8: run_task<T, 8, COMP>(a, tk); break;
-        case 16: run_task<T, 16, COMP>(a, tk); break;
-        case 32: run_task<T, 32, COMP>(a, tk); break;
+        case 4: run_task<T, 4, COMP, NBR>(a, tk); break;
+        case 8: run_task<T, 8, COMP, NBR>(a, tk); break;
+        case 16: run_task<T, 16, COMP, NBR>(a, tk); break;
+        case 32: run_task<T, 32, COMP, NBR>(a, tk); break;
         case 64:
-            if constexpr (sizeof(T) == 4 && !COMP) run_task<T, 64, COMP>(a, tk);
+            if constexpr (sizeof(T) == 4 && !COMP) run_task<T, 64, COMP, NBR>(a, tk);
             break;
         default: break;
         }
@@ -186,16 +222,22 @@ hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stre
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, a.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+#define GE_BK(T, C)                                                                         \
+    if (a.sync == 2)                                                                         \
+        hipLaunchKernelGGL((batch_kernel<T, C, true>), dim3(grid), dim3(kThreads), 0, stream, a); \
+    else                                                                                     \
+        hipLaunchKernelGGL((batch_kernel<T, C, false>), dim3(grid), dim3(kThreads), 0, stream, a);
     switch (prec) {
     case kFP64:
-        hipLaunchKernelGGL((batch_kernel<double, false>), dim3(grid), dim3(kThreads), 0, stream, a);
+        GE_BK(double, false)
         break;
     case kFP32:
-        hipLaunchKernelGGL((batch_kernel<float, false>), dim3(grid), dim3(kThreads), 0, stream, a);
+        GE_BK(float, false)
         break;
     case kFP32C:
-        hipLaunchKernelGGL((batch_kernel<float, true>), dim3(grid), dim3(kThreads), 0, stream, a);
+        GE_BK(float, true)
         break;
+#undef GE_BK
     default:
         return hipErrorInvalidValue;
     }

@@ -241,6 +241,7 @@ int device_grid()
 
 struct ge_batch_s {
     int prec;
+    int sync;               // 1: barrier per level, 2: neighbour flags
     int64_t nrods;
     int64_t total;          // offsets[nrods]
     int64_t estride;        // e block offset (FP32C)
@@ -424,6 +425,8 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
         return fail(GE_ERR_INVALID, "ge_batch_plan: a rod table pointer is NULL");
     if (d->precision < GE_FP64 || d->precision > GE_FP32_COMP)
         return fail(GE_ERR_INVALID, "ge_batch_plan: unknown precision %d", d->precision);
+    if (d->sync < 0 || d->sync > 2)
+        return fail(GE_ERR_INVALID, "ge_batch_plan: sync %d unknown", d->sync);
     const int prec = d->precision;
     const int64_t cap = (int64_t)kBatchWaves * 64 * ge::batch_max_k(prec);
     for (int64_t i = 0; i < d->nrods; ++i) {
@@ -472,6 +475,7 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
     if (!b)
         return fail(GE_ERR_NOMEM, "ge_batch_plan: out of host memory");
     b->prec = prec;
+    b->sync = d->sync == 0 ? 2 : d->sync;   // neighbour flags: faster in every precision
     b->nrods = d->nrods;
     b->total = d->offsets[d->nrods];
     b->estride = prec == ge::kFP32C ? ge::comp_offset(b->total) : 0;
@@ -571,6 +575,7 @@ ge_status ge_solve_batch(ge_batch_t b, void *u, void *workspace, int64_t step0, 
         a.step0 = parity;   // only the parity of the first level matters
         a.nsteps = (int32_t)nsteps;
         a.ntasks = b->ntasks;
+        a.sync = b->sync;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "ge_solve_batch: begin capture");

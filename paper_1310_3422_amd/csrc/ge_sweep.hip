@@ -358,6 +358,7 @@ hipError_t launch_tiles_persistent(int prec, int k, bool src, const TileArgs &a,
     case kFP64:
         if (k == 16) GE_P(double, 16, false);
         if (k == 32) GE_P(double, 32, false);
+        if (k == 64) GE_P(double, 64, false);
         break;
     case kFP32:
         if (k == 16) GE_P(float, 16, false);
@@ -373,7 +374,8 @@ hipError_t launch_tiles_persistent(int prec, int k, bool src, const TileArgs &a,
 
 bool persistent_supported(int prec, int k)
 {
-    return (prec == kFP64 && (k == 16 || k == 32)) || (prec == kFP32 && (k == 16 || k == 32)) ||
+    return (prec == kFP64 && (k == 16 || k == 32 || k == 64)) ||
+           (prec == kFP32 && (k == 16 || k == 32)) ||
            (prec == kFP32C && k == 16);
 }
 
@@ -382,7 +384,7 @@ bool tile_config_supported(int prec, int k, int nw)
     if (nw != 1 && nw != 4)
         return false;
     switch (prec) {
-    case kFP64: return k == 2 || k == 4 || k == 8 || k == 16 || k == 32;
+    case kFP64: return k == 2 || k == 4 || k == 8 || k == 16 || k == 32 || k == 64;
     case kFP32: return k == 4 || k == 8 || k == 16 || k == 32;
     case kFP32C: return k == 4 || k == 8 || k == 16;
     default: return false;
@@ -399,6 +401,7 @@ hipError_t launch_tiles(int prec, int k, int nw, bool src, const TileArgs &a,
         if (k == 8) return launch_nw<double, 8, false>(nw, src, a, stream);
         if (k == 16) return launch_nw<double, 16, false>(nw, src, a, stream);
         if (k == 32) return launch_nw<double, 32, false>(nw, src, a, stream);
+        if (k == 64) return launch_nw<double, 64, false>(nw, src, a, stream);
         break;
     case kFP32:
         if (k == 4) return launch_nw<float, 4, false>(nw, src, a, stream);

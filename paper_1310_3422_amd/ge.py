@@ -32,7 +32,7 @@ class GeDesc(ctypes.Structure):
 class GeBatchDesc(ctypes.Structure):
     _fields_ = [("nrods", _i64), ("n", _vp), ("offsets", _vp), ("r", _vp),
                 ("g_left", _vp), ("g_right", _vp), ("precision", _i32),
-                ("tune", _i32)]
+                ("tune", _i32), ("sync", _i32)]
 
 
 class GEError(RuntimeError):
@@ -258,7 +258,7 @@ class Batch:
     graph-captured launch.  Host arrays describe the rods; the packed state
     lives in a device tensor (see ``pack_batch_state``)."""
 
-    def __init__(self, n, offsets, r, g_left, g_right, precision="fp32", tune=False):
+    def __init__(self, n, offsets, r, g_left, g_right, precision="fp32", tune=False, sync=0):
         self.n = np.ascontiguousarray(n, dtype=np.int64)
         self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         self.r = np.ascontiguousarray(r, dtype=np.float64)
@@ -271,7 +271,8 @@ class Batch:
         c = lambda a: ctypes.c_void_p(a.ctypes.data)
         self.desc = GeBatchDesc(nrods=nr, n=c(self.n), offsets=c(self.offsets), r=c(self.r),
                                 g_left=c(self.g_left), g_right=c(self.g_right),
-                                precision=self.precision, tune=1 if tune else 0)
+                                precision=self.precision, tune=1 if tune else 0,
+                                sync=int(sync))
         h = _vp()
         check(lib().ge_batch_plan(ctypes.byref(h), ctypes.byref(self.desc)))
         self.handle = h
@@ -279,9 +280,9 @@ class Batch:
         self.workspace_bytes = int(lib().ge_batch_workspace_bytes(h))
 
     @classmethod
-    def from_inputs(cls, rb, precision="fp32", tune=False):
+    def from_inputs(cls, rb, precision="fp32", tune=False, sync=0):
         """From an ``inputs.RodBatch``."""
-        return cls(rb.n, rb.offsets, rb.r, rb.g_left, rb.g_right, precision, tune)
+        return cls(rb.n, rb.offsets, rb.r, rb.g_left, rb.g_right, precision, tune, sync)
 
     def __del__(self):
         h = getattr(self, "handle", None)

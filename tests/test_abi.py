@@ -162,7 +162,7 @@ def test_halo_of_depth_plus_one_is_enough_and_tight(depth, step0):
         assert cut[lo - 1] != full[a + lo - 1] and cut[hi] != full[a + hi]
 
 
-def _batch_desc(n, offsets, r=None, gl=None, gr=None, precision=1, tune=0):
+def _batch_desc(n, offsets, r=None, gl=None, gr=None, precision=1, tune=0, sync=0):
     nr = len(n)
     arrs = dict(n=np.asarray(n, np.int64), offsets=np.asarray(offsets, np.int64),
                 r=np.asarray(r if r is not None else [1.0] * nr, np.float64),
@@ -171,7 +171,7 @@ def _batch_desc(n, offsets, r=None, gl=None, gr=None, precision=1, tune=0):
     c = lambda a: ctypes.c_void_p(a.ctypes.data)
     d = ge.GeBatchDesc(nrods=nr, n=c(arrs["n"]), offsets=c(arrs["offsets"]), r=c(arrs["r"]),
                        g_left=c(arrs["gl"]), g_right=c(arrs["gr"]), precision=precision,
-                       tune=tune)
+                       tune=tune, sync=sync)
     return d, arrs
 
 
@@ -182,6 +182,8 @@ def _batch_desc(n, offsets, r=None, gl=None, gr=None, precision=1, tune=0):
     (dict(n=[100, 50], offsets=[0, 100, 200], r=[1.0, 0.0]), ge.GE_ERR_INVALID),
     (dict(n=[100, 50], offsets=[0, 100, 200], r=[1.0, float("nan")]), ge.GE_ERR_NONFINITE),
     (dict(n=[70000], offsets=[0, 70000]), ge.GE_ERR_UNSUPPORTED),        # above FP32 on-chip limit
+    (dict(n=[100], offsets=[0, 100], sync=3), ge.GE_ERR_INVALID),
+    (dict(n=[100], offsets=[0, 100], sync=-1), ge.GE_ERR_INVALID),
     (dict(n=[40000], offsets=[0, 40000], precision=0), ge.GE_ERR_UNSUPPORTED),
     (dict(n=[100], offsets=[0, 100], precision=9), ge.GE_ERR_INVALID),
 ])

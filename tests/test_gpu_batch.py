@@ -23,8 +23,8 @@ def rel_l2(x, y):
     return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
 
 
-def run_batch(rb, precision, nsteps, step0=0, tune=False):
-    b = ge.Batch.from_inputs(rb, precision, tune=tune)
+def run_batch(rb, precision, nsteps, step0=0, tune=False, sync=0):
+    b = ge.Batch.from_inputs(rb, precision, tune=tune, sync=sync)
     u = ge.pack_batch_state(rb.u0, rb.offsets, rb.n, precision)
     ws = b.new_workspace()
     b.solve(u, step0, nsteps, ws)
@@ -37,11 +37,12 @@ def start_rod(rb, i, precision):
     return ge.unpack_batch_rod(u, rb.offsets, rb.n, i, precision)
 
 
+@pytest.mark.parametrize("sync", [1, 2])
 @pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32c"])
-def test_small_batch_parity(precision):
+def test_small_batch_parity(precision, sync):
     rb = inputs.rod_batch(seed=11, nrods=48, nmin=1, nmax=20000, align=4)
     nsteps = 120
-    b, got = run_batch(rb, precision, nsteps, step0=1)
+    b, got = run_batch(rb, precision, nsteps, step0=1, sync=sync)
     tol = {"fp64": 1e-12, "fp32": 2e-5, "fp32c": 1e-6}[precision]
     for i in range(rb.nrods):
         v0 = start_rod(rb, i, precision)
@@ -51,11 +52,12 @@ def test_small_batch_parity(precision):
         assert rel_l2(g, want) < tol, (i, int(rb.n[i]))
 
 
+@pytest.mark.parametrize("sync", [1, 2])
 @pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32c"])
-def test_batch_matches_single_rod_bitwise(precision):
+def test_batch_matches_single_rod_bitwise(precision, sync):
     rb = inputs.rod_batch(seed=12, nrods=24, nmin=3, nmax=30000, align=4)
     nsteps = 57
-    b, got = run_batch(rb, precision, nsteps, step0=2)
+    b, got = run_batch(rb, precision, nsteps, step0=2, sync=sync)
     ks = b.info()["rod_k"]
     assert len(set(ks.tolist())) >= 2   # several points-per-lane choices in play
     for i in range(rb.nrods):

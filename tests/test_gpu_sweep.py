@@ -130,7 +130,7 @@ def test_bitwise_invariance_across_tiling_depth_and_calls(precision):
     n, s = 30011, 40
     rng = np.random.default_rng(17)
     u0 = inputs.sine_rod(n, 17) + 0.05 * rng.standard_normal(n)
-    tiles = {"fp64": (2, 4, 8, 16, 32), "fp32": (4, 8, 16, 32), "fp32c": (4, 8, 16)}[precision]
+    tiles = {"fp64": (2, 4, 8, 16, 32, 64), "fp32": (4, 8, 16, 32), "fp32c": (4, 8, 16)}[precision]
     results = []
     for tile in tiles:
         for waves in (1, 4):
@@ -276,7 +276,7 @@ def test_single_rod_2p27_moving_walls_sampled(precision):
 
 
 # ------------------------------------------------- persistent schedule ----
-@pytest.mark.parametrize("precision,tile", [("fp64", 16), ("fp64", 32), ("fp32", 16),
+@pytest.mark.parametrize("precision,tile", [("fp64", 16), ("fp64", 32), ("fp64", 64), ("fp32", 16),
                                             ("fp32", 32), ("fp32c", 16)])
 def test_persistent_schedule_is_bitwise_the_per_tile_schedule(precision, tile):
     """The persistent kernel sweeps the same tiles with the same arithmetic:

@@ -29,7 +29,7 @@ using namespace dev;
 constexpr int kFP = 512;                   // output points per workgroup
 constexpr int kFHalo = 64;                 // computed rows beyond each side (= 2 x sum of spacings)
 constexpr int kFR = kFP + 2 * kFHalo;      // rows computed per layer (40 M-tiles)
-constexpr int kFWaves = 4;                 // 10 M-tiles of 16 rows per wave
+constexpr int kFWaves = 8;                 // 5 M-tiles of 16 rows per wave, two waves per SIMD
 constexpr int kFMT = kFR / 16 / kFWaves;
 constexpr int kFPad = 2 * kMaxDil;         // LDS rows beyond the computed rows on each side
 constexpr int kFRows = kFR + 2 * kFPad;
@@ -40,16 +40,45 @@ static_assert(kFR % (16 * kFWaves) == 0, "rows per wave");
 // LDS row i holds position w0 - kFHalo - kFPad + i; computed row q is LDS
 // row q + kFPad.
 
-// Weights of one layer, packed [5][cout][cin] bf16, into LDS rows of kFXS.
+// One layer's packed weights ([5][cout][cin] bf16), staged through
+// registers: fetch() issues every global load of the thread's share at
+// once, store() writes them to LDS rows of kFXS later, so the loads of the
+// next layer overlap the current layer's matrix work.
 template <int CIN, int COUT>
-__device__ __forceinline__ void load_weights(bf16 *ws, const bf16 *wt, int tid)
-{
-    constexpr int CPR = CIN / 8;
-    for (int i = tid; i < kTaps * COUT * CPR; i += kFThreads) {
-        const int row = i / CPR, ch = (i % CPR) * 8;
-        copy16(&ws[row * kFXS + ch], &wt[row * CIN + ch]);
+struct WeightStage {
+    static constexpr int CPR = CIN / 8;                  // 16-byte chunks per row
+    static constexpr int TOTAL = kTaps * COUT * CPR;
+    static constexpr int N = (TOTAL + kFThreads - 1) / kFThreads;
+    // one vector of 4N words (a plain array here ends up in scratch memory)
+    typedef uint32_t Vec __attribute__((ext_vector_type(4 * N)));
+    Vec v;
+    __device__ __forceinline__ void fetch(const bf16 *wt, int tid)
+    {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int i = tid + j * kFThreads;
+            if (TOTAL % kFThreads == 0 || i < TOTAL) {
+                const uint4 x = *reinterpret_cast<const uint4 *>(&wt[(i / CPR) * CIN + (i % CPR) * 8]);
+                v[4 * j] = x.x;
+                v[4 * j + 1] = x.y;
+                v[4 * j + 2] = x.z;
+                v[4 * j + 3] = x.w;
+            }
+        }
+        // keep the loads here, ahead of the work they are meant to overlap
+        __builtin_amdgcn_sched_barrier(0);
     }
-}
+    __device__ __forceinline__ void store(bf16 *ws, int tid) const
+    {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int i = tid + j * kFThreads;
+            if (TOTAL % kFThreads == 0 || i < TOTAL)
+                *reinterpret_cast<uint4 *>(&ws[(i / CPR) * kFXS + (i % CPR) * 8]) =
+                    make_uint4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+        }
+    }
+};
 
 // acc[m][n] += conv of the activations with the layer's weights for the
 // wave's M-tiles: same k-outer, channel-chunk-inner order as conv_kernel.
@@ -91,11 +120,50 @@ __device__ __forceinline__ void layer_mfma(const bf16 *act, const bf16 *ws, int 
     }
 }
 
+// The six-layer epilogue of a GELU layer for the wave's M-tiles: bias,
+// GELU, the residual (layers 2..5), zero outside the rod, written in place
+// as four consecutive channels per lane.
+template <bool RES>
+__device__ __forceinline__ void gelu_epilogue(bf16 *act, const f32x4 (&acc)[kFMT][4],
+                                              const float *bias, int wv, int lane, int w0,
+                                              int W)
+{
+    const int r16 = lane & 15, g4 = lane >> 4;
+    float bl[4][4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bl[n][j] = bias[16 * n + 4 * g4 + j];
+#pragma unroll
+    for (int m = 0; m < kFMT; ++m) {
+        const int q = 16 * (kFMT * wv + m) + r16;          // computed row (position)
+        const int w = w0 - kFHalo + q;
+        const bool in = w >= 0 && w < W;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            bf16x4 *dst = reinterpret_cast<bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]);
+            bf16x4 hv;
+            if (RES) hv = *dst;
+            bf16x4 o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float h = gelu(acc[m][n][j] + bl[n][j]);
+                if (RES) h += bf2f(hv[j]);
+                o[j] = in ? f2bf(h) : f2bf(0.f);
+            }
+            *dst = o;
+        }
+        // one M-tile at a time: no hoisting of later tiles' reads, which
+        // would crowd out the registers of the weights in flight
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
 {
     __shared__ __attribute__((aligned(16))) bf16 act[kFRows * kFXS];
     __shared__ __attribute__((aligned(16))) bf16 ws[kTaps * 64 * kFXS];
-    __shared__ float bias[64];
+    __shared__ float bias[6][64];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -108,75 +176,86 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
     const float rb = a.r[b];
     const float rn = (rb - 1.25f) / 0.75f;
 
-    // features of every LDS row (zero outside the rod), channels 2..63 zero
-    for (int i = tid; i < kFRows; i += kFThreads) {
-        const int w = w0 - kFHalo - kFPad + i;
-        bf16 *row = &act[i * kFXS];
-        float f0 = 0.f, f1 = 0.f;
-        if (w >= 0 && w < W) {
-            const float um = w > 0 ? ub[w - 1] : 0.f, up = w < W - 1 ? ub[w + 1] : 0.f;
-            const float d = (um - ub[w]) + (up - ub[w]);
-            f0 = d / sc;
-            f1 = rn;
+    {
+        WeightStage<32, 64> w1;
+        w1.fetch(static_cast<const bf16 *>(a.w[0]), tid);
+        // features of every LDS row (zero outside the rod), channels 2..63
+        // zero, written as 16-byte chunks
+        for (int i = tid; i < kFRows; i += kFThreads) {
+            const int w = w0 - kFHalo - kFPad + i;
+            float f0 = 0.f, f1 = 0.f;
+            if (w >= 0 && w < W) {
+                const float um = w > 0 ? ub[w - 1] : 0.f, up = w < W - 1 ? ub[w + 1] : 0.f;
+                const float d = (um - ub[w]) + (up - ub[w]);
+                f0 = d / sc;
+                f1 = rn;
+            }
+            uint4 *row = reinterpret_cast<uint4 *>(&act[i * kFXS]);
+            const uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, f2bf(f0)) |
+                                ((uint32_t)__builtin_bit_cast(uint16_t, f2bf(f1)) << 16);
+            row[0] = make_uint4(lo, 0, 0, 0);
+#pragma unroll
+            for (int c = 1; c < 8; ++c) row[c] = make_uint4(0, 0, 0, 0);
         }
-        row[0] = f2bf(f0);
-        row[1] = f2bf(f1);
-        for (int c = 2; c < 64; ++c) row[c] = f2bf(0.f);
+        for (int i = tid; i < 6 * 64; i += kFThreads) {
+            const int l = i / 64, c = i % 64;
+            bias[l][c] = (l < 5 || c < 16) ? a.bias[l][c] : 0.f;
+        }
+        w1.store(ws, tid);
     }
-    load_weights<32, 64>(ws, static_cast<const bf16 *>(a.w[0]), tid);
-    if (tid < 64) bias[tid] = a.bias[0][tid];
     __syncthreads();
 
-    const int r16 = lane & 15, g4 = lane >> 4;
-    // layers 1..5 (GELU; residual from layer 2 on)
+    // layers 1..5 (GELU; residual from layer 2 on).  The next layer's
+    // weights are fetched once every wave is past the matrix work (its
+    // registers are free then) and written to LDS after the epilogue, so the
+    // loads overlap the epilogue.
     {
         f32x4 acc[kFMT][4];
-        layer_mfma<32, 64>(act, ws, wv, lane, a.dil[0], acc);
-#pragma unroll 1
-        for (int l = 0; l < 5; ++l) {
+        {
+            layer_mfma<32, 64>(act, ws, wv, lane, a.dil[0], acc);
             __syncthreads();   // every wave has finished reading act and ws
-            float bl[4][4];
-#pragma unroll
-            for (int n = 0; n < 4; ++n)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bl[n][j] = bias[16 * n + 4 * g4 + j];
-            // the next layer's weights load while the epilogue runs
-            if (l < 4)
-                load_weights<64, 64>(ws, static_cast<const bf16 *>(a.w[l + 1]), tid);
-            else
-                load_weights<64, 16>(ws, static_cast<const bf16 *>(a.w[5]), tid);
-#pragma unroll
-            for (int m = 0; m < kFMT; ++m) {
-                const int q = 16 * (kFMT * wv + m) + r16;          // computed row (position)
-                const int w = w0 - kFHalo + q;
-                const bool in = w >= 0 && w < W;
-#pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    bf16x4 *dst = reinterpret_cast<bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]);
-                    bf16x4 hv;
-                    if (l > 0) hv = *dst;
-                    bf16x4 o;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        float h = gelu(acc[m][n][j] + bl[n][j]);
-                        if (l > 0) h += bf2f(hv[j]);
-                        o[j] = in ? f2bf(h) : f2bf(0.f);
-                    }
-                    *dst = o;
-                }
+            WeightStage<64, 64> nx;
+            nx.fetch(static_cast<const bf16 *>(a.w[1]), tid);
+            gelu_epilogue<false>(act, acc, bias[0], wv, lane, w0, W);
+            nx.store(ws, tid);
+            __syncthreads();
+        }
+#pragma unroll 1
+        for (int l = 1; l < 5; ++l) {
+            layer_mfma<64, 64>(act, ws, wv, lane, a.dil[l], acc);
+            if (l < 4) {
+                __syncthreads();
+                WeightStage<64, 64> nx;
+                nx.fetch(static_cast<const bf16 *>(a.w[l + 1]), tid);
+                gelu_epilogue<true>(act, acc, bias[l], wv, lane, w0, W);
+                nx.store(ws, tid);
+            } else {
+                __syncthreads();
+                WeightStage<64, 16> nx;
+                nx.fetch(static_cast<const bf16 *>(a.w[5]), tid);
+                gelu_epilogue<true>(act, acc, bias[l], wv, lane, w0, W);
+                nx.store(ws, tid);
             }
             __syncthreads();   // activations and weights are in place
-            if (tid < 64) bias[tid] = (l < 4) ? a.bias[l + 1][tid] : (tid < 16 ? a.bias[5][tid] : 0.f);
-            __syncthreads();
-            if (l < 4) layer_mfma<64, 64>(act, ws, wv, lane, a.dil[l + 1], acc);
         }
     }
-    // layer 6 (64 -> 1, padded to 16 outputs) and the jump
+    // layer 6 (64 -> 1, padded to 16 outputs) and the jump; the lanes that
+    // write (channel 0) load their points of u first, to overlap the matrix
+    // work
+    const int r16 = lane & 15, g4 = lane >> 4;
+    float uo[kFMT];
+#pragma unroll
+    for (int m = 0; m < kFMT; ++m) {
+        const int p = 16 * (kFMT * wv + m) + r16 - kFHalo;   // point within the tile
+        const int w = w0 + p;
+        uo[m] = (g4 == 0 && p >= 0 && p < kFP && w < W) ? ub[w] : 0.f;
+    }
+    __builtin_amdgcn_sched_barrier(0);
     f32x4 acc6[kFMT][1];
     layer_mfma<64, 16>(act, ws, wv, lane, a.dil[5], acc6);
     if (g4 == 0) {
         // channel 0 of position 16 (M-tile) + r16
-        const float b0 = bias[0];
+        const float b0 = bias[5][0];
         const float amp = 64.0f * rb * sc;
 #pragma unroll
         for (int m = 0; m < kFMT; ++m) {
@@ -185,7 +264,7 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
             const int w = w0 + p;
             if (p >= 0 && p < kFP && w < W) {
                 const float out = acc6[m][0][0] + b0;
-                a.u_next[base + w] = ub[w] + amp * out;
+                a.u_next[base + w] = uo[m] + amp * out;
             }
         }
     }

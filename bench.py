@@ -118,10 +118,28 @@ def cpu_baseline(u0, target_s):
     t = time.perf_counter()
     oracle.step_n(u0, R, levels, nthreads=threads)
     dt = time.perf_counter() - t
+    # the single-thread form (the paper's one-core comparison), on a few
+    # levels, extrapolated per update
+    lv1 = max(2, min(levels, int(0.2 * target_s / (per_level * threads))))
+    t = time.perf_counter()
+    oracle.step_n(u0, R, lv1, nthreads=1)
+    dt1 = time.perf_counter() - t
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n * levels / dt, "unit": "updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"same rod (N={n}), first {levels} of {LEVELS} levels, FP64 C oracle, "
-                      f"{threads} threads with a barrier per level, {dt:.1f} s"}
+                      f"{threads} threads with a barrier per level, {dt:.1f} s",
+            "single_thread": {"value": n * lv1 / dt1, "unit": "updates/s",
+                              "sample": f"first {lv1} levels, 1 thread, {dt1:.1f} s "
+                                        "(rate extrapolated to the whole run)"},
+            "host_cpu": model}
 
 
 def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
@@ -382,7 +400,15 @@ def main():
 
     if not args.no_cpu:
         print(f"[bench] CPU baseline (~{args.cpu_seconds:.0f} s) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(u0, args.cpu_seconds)
+        cb = cpu_baseline(u0, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        # the paper's own comparison (a laptop GPU against one and eight CPU
+        # threads of its host, same sweep), as context for these ratios
+        out["gpu_over_cpu"] = {
+            "all_cores": round(value / cb["value"], 1),
+            "single_thread": round(value / cb["single_thread"]["value"], 1),
+            "paper_context": "GT 335M vs i7-720QM: about 5x over 1 thread, about 2x over "
+                             "8 threads (sub-domain scheme, relative figures only)"}
 
     print(json.dumps(out), flush=True)
     return 0

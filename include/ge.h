@@ -183,10 +183,14 @@ typedef struct {
                              /* store it (file $GE_TUNE_CACHE, default        */
                              /* ~/.cache/libge/batch_tune.txt); 0: use the    */
                              /* stored measurement, or built-in defaults      */
-    int32_t sync;            /* how the waves of a rod meet every level:      */
-                             /* 0 = library choice, 1 = workgroup barrier,    */
-                             /* 2 = each wave waits for its two neighbours    */
-                             /* only (level flags in LDS)                     */
+    int32_t sync;            /* how the waves of a rod exchange edge values:  */
+                             /* 0 = library choice, 1 = every level, at a     */
+                             /* workgroup barrier, 2 = every level, each wave */
+                             /* waiting for its two neighbours only (level    */
+                             /* flags in LDS), 3 = neighbouring waves overlap */
+                             /* by one lane, refreshed at a barrier every K-1 */
+                             /* levels (rods whose overlapping waves do not   */
+                             /* fit a workgroup fall back to 2)               */
 } ge_batch_desc;
 
 /* Create a batch plan: choose points per lane for every rod, bundle rods

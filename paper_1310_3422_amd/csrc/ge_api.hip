@@ -80,6 +80,41 @@ int64_t state_elems(int prec, int64_t n)
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Library defaults, measured on MI355X on rods of 2^24 points without a
+// source and of 2^27 points with moving walls and a source.  At a few levels
+// per launch the sweep streams HBM, and narrow per-lane rows (one or two
+// 16-byte chunks) coalesce best; deep launches are issue-bound and want wide
+// rows, few halo points and no workgroup barrier.  With a source profile the
+// persistent schedule's second register copy of the profile costs more than
+// its prefetch gains, so those rods stay on one workgroup per tile.
+struct Choice {
+    int tile, waves, depth;
+};
+
+Choice default_choice(int prec, int depth, bool src)
+{
+    if (prec == ge::kFP32C) {
+        if (depth == 0) return {16, 4, 128};
+        if (depth <= 4) return {4, 1, depth};
+        return {depth <= 64 ? 8 : 16, 4, depth};
+    }
+    const bool f64 = prec == ge::kFP64;
+    if (depth == 0) return src ? Choice{16, 1, 64} : Choice{32, 1, 96};
+    if (depth <= 4) return {f64 ? 2 : 4, 1, depth};
+    if (depth <= 8) return {(f64 || !src) ? (f64 ? 4 : 8) : 4, 1, depth};
+    if (depth <= 16) return {f64 ? (src ? 4 : 8) : 16, 1, depth};
+    if (depth <= 32 || src) return {16, 1, depth};
+    return {32, 1, depth};
+}
+
+// Whether the persistent schedule is the faster one for a single-wave tile:
+// deep launches without a source, with rows of 32 points (FP64 also 16).
+bool persistent_pays(int prec, int tile, int waves, int depth, bool src)
+{
+    return waves == 1 && !src && depth > 32 && prec != ge::kFP32C &&
+           ge::persistent_supported(prec, tile) && (tile >= 32 || prec == ge::kFP64);
+}
+
 }  // namespace
 
 struct ge_plan_s {
@@ -148,22 +183,18 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
 
     const int prec = d->precision;
     int tile = d->tile, waves = d->waves, depth = d->depth;
-    // Defaults measured on MI355X on a rod of 2^24 points: FP64 runs best
-    // with 32 points per lane, one wave per workgroup, 96 levels per launch
-    // and the persistent schedule; both FP32 forms with 16 points per lane,
-    // four waves (4096-point windows) and 128 levels.  A depth left at 0 is
-    // clipped so that the halo stays within a quarter of the window.
-    const bool wide = prec != ge::kFP64;
-    if (depth == 1) {
-        // one level per launch is a pure stream: small tiles (one 16-byte
-        // chunk per lane) and single-wave workgroups move the most bytes
-        if (tile == 0) tile = wide ? 4 : 2;
-        if (waves == 0) waves = 1;
+    const bool src = d->src_b != nullptr;
+    if (depth < 0)
+        return fail(GE_ERR_INVALID, "ge_plan: depth = %d, need depth >= 1", depth);
+    const Choice ch = default_choice(prec, depth, src);
+    if (tile == 0) {
+        tile = ch.tile;
+        if (waves == 0) waves = ch.waves;
     }
-    if (tile == 0) tile = wide ? 16 : 32;
-    if (waves == 0) waves = wide ? 4 : 1;
+    if (waves == 0) waves = prec == ge::kFP32C ? 4 : 1;
     if (depth == 0) {
-        depth = wide ? 128 : 96;
+        // clipped so that the halo stays within a quarter of the window
+        depth = ch.depth;
         const int al = (prec == ge::kFP64) ? 2 : 4;
         while (depth > 1 && 4 * round_up(depth + 1, al) > (int64_t)waves * 64 * tile) --depth;
     }
@@ -214,8 +245,8 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
     }
     // the library's choice: persistent wherever it is built and the rod has
     // enough tiles for the prefetch to matter
-    const bool auto_persistent = d->schedule == 0 && waves == 1 && prec == ge::kFP64 &&
-                                 ge::persistent_supported(prec, tile) && p->ntiles >= 64;
+    const bool auto_persistent = d->schedule == 0 && persistent_pays(prec, tile, waves, p->depth, src) &&
+                                 p->ntiles >= 64;
     p->persistent = !p->single && p->ntiles >= 3 && (d->schedule == 2 || auto_persistent);
     const double r = p->r;
     p->h = 1.0 / (double)(p->n + 1);

@@ -18,9 +18,12 @@ struct BatchRod {
 
 // One unit of work for a workgroup: rods sharing points-per-lane k, each
 // owning a contiguous range of the workgroup's waves (-1: wave idle).
+// halo = 1: the rods' waves overlap by one lane on each side and exchange
+// those lanes every k-1 levels; halo = 0: adjacent waves exchange their edge
+// values every level.
 struct BatchTask {
     int32_t k;
-    int32_t pad;
+    int32_t halo;
     int32_t wave_rod[kBatchWaves];   // rod index per wave
     int32_t wave_idx[kBatchWaves];   // wave index within its rod
 };
@@ -34,9 +37,19 @@ struct BatchArgs {
     int64_t step0;
     int32_t nsteps;
     int32_t ntasks;
-    int32_t sync;             // 1: workgroup barrier per level; 2: neighbour flags
+    int32_t sync;             // 1: workgroup barrier per level; 2: neighbour flags;
+                              // 3: halo lanes (tasks with halo = 0 use flags)
     int32_t pad;
 };
+
+// Waves a rod of n points needs at k points per lane when neighbouring
+// waves overlap by one lane (halo tasks): 64k points for the first wave and
+// 62k new points for each further one.
+inline int halo_waves(int64_t n, int k)
+{
+    const int64_t w = 64 * (int64_t)k, c = 62 * (int64_t)k;
+    return n <= w ? 1 : (int)(1 + (n - w + c - 1) / c);
+}
 
 hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream);
 int batch_max_k(int prec);

@@ -76,7 +76,7 @@ __device__ __forceinline__ void rod_levels(const BatchArgs &a, const BatchRod &r
     T gl_hi, gl_lo, gr_hi, gr_lo;
     split_wall<T, COMP>(rd.gl, gl_hi, gl_lo);
     split_wall<T, COMP>(rd.gr, gr_hi, gr_lo);
-    const Coef<T> cf{(T)rd.c1, (T)rd.c2, (T)rd.cs, T(0), T(0), T(0)};
+    const Coef<T> cf = lane_coef(Coef<T>{(T)rd.c1, (T)rd.c2, (T)rd.cs, T(0), T(0), T(0)});
     const T b0[K] = {};
     FluxTap ft{false, 0.0, 0.0, 1.0, 0.0};
 
@@ -187,10 +187,174 @@ __device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk
     __syncthreads();   // LDS slots are reused by the next task
 }
 
-template <typename T, bool COMP, bool NBR>
+// ---- halo-lane tasks ------------------------------------------------------
+// Wave j of a rod holds the window [62 k j, 62 k j + 64 k): its lanes 0 and
+// 63 duplicate the neighbouring waves' lanes 62 and 1.  A level-(m+1) value
+// depends on level-m values at most two places away, and a value that is
+// wrong at an open window edge spreads inward by at most one point per
+// level after the first, so after the duplicated lanes are refreshed the
+// wave can advance k-1 levels on its own (wave-edge values entering as zero)
+// and lanes 1..62 stay exact.  The refresh goes through LDS with one
+// workgroup barrier every k-1 levels instead of an exchange every level.
+// Walls stay exact at the rod's ends: the first wave has no left duplicate
+// and the last holds the right wall, as in the per-level form.
+constexpr int kMaxBatchK = 64;
+
+template <typename T, int K, bool COMP, bool WALL>
+__device__ __forceinline__ void rod_block(const BatchRod &rd, int wr, int64_t ws, T (&s)[K],
+                                          T (&e)[K], int64_t level0, int nlev)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t n = rd.n;
+    const int64_t q = n - ws;                         // window position of the right wall node
+    const bool left_wall = (wr == 0);
+    const bool ghost_in = (q >= 0) && (q < (int64_t)kWave * K);
+    const bool ghost_edge = (q == (int64_t)kWave * K);
+    const int kR = ghost_in ? (int)(q % K) : 0;
+    const int lR = ghost_in ? (int)(q / K) : -1;
+    const int64_t qS = q - 1;
+    const bool has_S = (qS >= 0) && (qS < (int64_t)kWave * K);
+    const int kS = has_S ? (int)(qS % K) : 0;
+    const int lS = has_S ? (int)(qS / K) : -1;
+    T gl_hi, gl_lo, gr_hi, gr_lo;
+    split_wall<T, COMP>(rd.gl, gl_hi, gl_lo);
+    split_wall<T, COMP>(rd.gr, gr_hi, gr_lo);
+    const Coef<T> cf = lane_coef(Coef<T>{(T)rd.c1, (T)rd.c2, (T)rd.cs, T(0), T(0), T(0)});
+    const T b0[K] = {};
+    FluxTap ft{false, 0.0, 0.0, 1.0, 0.0};
+
+    for_levels(level0, nlev, [&](auto par, int) {
+        constexpr int p = decltype(par)::value;
+        if (WALL && ghost_in) {
+            put_at<T, K>(s, kR, lane == lR, gr_hi);
+            if constexpr (COMP) put_at<T, K>(e, kR, lane == lR, gr_lo);
+        }
+        // fills at a wall edge are the wall value; at an open edge they
+        // only reach the duplicated lane
+        T xl = T(0), xr = T(0), yl = T(0), yr = T(0);
+        WallLevel<T> wlv{false, T(0)};
+        bool singR = false;
+        if constexpr (WALL) {
+            if (left_wall) { xl = gl_hi; if constexpr (COMP) yl = gl_lo; }
+            if (ghost_edge) { xr = gr_hi; if constexpr (COMP) yr = gr_lo; }
+            wlv.isL = left_wall && (p == 1) && (lane == 0);
+            singR = has_S && (((n - 1 + p) & 1) == 0);
+        }
+        Lone<T> lone{T(0), T(0)};
+        if (WALL && singR)
+            lone = right_lone<T, K, COMP, false>(s, e, b0, kS, xl, yl, gr_hi, gr_lo, T(0), cf,
+                                                 T(0));
+        ge_level<T, K, COMP, false, WALL, p, !WALL>(s, e, b0, T(0), T(0), xl, T(0), xr, T(0), yl,
+                                                    T(0), yr, T(0), cf, T(0), wlv, ft);
+        if (WALL && singR) {
+            put_at<T, K>(s, kS, lane == lS, lone.s);
+            if constexpr (COMP) put_at<T, K>(e, kS, lane == lS, lone.e);
+        }
+    });
+}
+
+// The levels of a halo-lane task for one wave, in blocks of K-1 levels with
+// the duplicated lanes refreshed between blocks.  hx: [2 buffers][waves]
+// [2 slots][kMaxBatchK] values of s (he: of e, for the pair); slot 0
+// carries lane 62 to the right neighbour, slot 1 lane 1 to the left one.
+// MODE: 0 = a wave without a rod (it only passes the barriers), 1 = both
+// window edges open, 2 = a wave holding a wall.  Every wave of the
+// workgroup passes the same barriers (all rods of a task share K and the
+// level count); the mode is chosen once per wave, outside the block loop,
+// so each wave runs one instantiation of the level code.
+template <typename T, int K, bool COMP, int MODE>
+__device__ __forceinline__ void halo_blocks(const BatchArgs &a, const BatchRod &rd, int w, int wr,
+                                            int64_t ws, bool hasL, bool hasR, T (&s)[K],
+                                            T (&e)[K], T *hx, T *he)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    auto slot = [&](int buf, int wave, int which) {
+        return ((buf * kWaves + wave) * 2 + which) * kMaxBatchK;
+    };
+    int64_t done = 0;
+    for (int blk = 0;; ++blk) {
+        const int nb = (int)((a.nsteps - done) < (K - 1) ? (a.nsteps - done) : (K - 1));
+        if constexpr (MODE != 0)
+            rod_block<T, K, COMP, MODE == 2>(rd, wr, ws, s, e, a.step0 + done, nb);
+        done += nb;
+        if (done >= a.nsteps)
+            break;
+        const int pb = blk & 1;
+        if (MODE != 0 && (lane == kWave - 2 || lane == 1)) {
+            const int o = slot(pb, w, lane == 1 ? 1 : 0);
+#pragma unroll
+            for (int j = 0; j < K; ++j) hx[o + j] = s[j];
+            if constexpr (COMP) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) he[o + j] = e[j];
+            }
+        }
+        __syncthreads();
+        if (MODE != 0 && ((lane == 0 && hasL) || (lane == kWave - 1 && hasR))) {
+            const int o = lane == 0 ? slot(pb, w - 1, 0) : slot(pb, w + 1, 1);
+#pragma unroll
+            for (int j = 0; j < K; ++j) s[j] = hx[o + j];
+            if constexpr (COMP) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) e[j] = he[o + j];
+            }
+        }
+    }
+}
+
+template <typename T, int K, bool COMP>
+__device__ __forceinline__ void run_task_halo(const BatchArgs &a, const BatchTask &tk, T *hx,
+                                              T *he)
+{
+    static_assert(K >= 4 && K <= kMaxBatchK, "points per lane");
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int rod = tk.wave_rod[w];
+    const int wr = tk.wave_idx[w];
+    const bool hasR = rod >= 0 && w + 1 < kWaves && tk.wave_rod[w + 1] == rod;
+    const bool hasL = rod >= 0 && wr > 0;
+    T s[K], e[K];
+    BatchRod rd{};
+    T *us = nullptr, *ue = nullptr;
+    const int64_t ws = (int64_t)wr * 62 * K;          // window start (even)
+    const int64_t g0 = ws + (int64_t)lane * K;
+    if (rod >= 0) {
+        rd = a.rods[rod];
+        us = static_cast<T *>(a.u) + rd.off;
+        ue = static_cast<T *>(a.u) + a.estride + rd.off;
+        load_lane_guarded<T, K>(us + g0, g0, rd.n, s);
+        if constexpr (COMP) load_lane_guarded<T, K>(ue + g0, g0, rd.n, e);
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) s[j] = T(0);
+    }
+    if constexpr (!COMP) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) e[j] = T(0);
+    }
+    if (rod < 0)
+        halo_blocks<T, K, COMP, 0>(a, rd, w, wr, ws, hasL, hasR, s, e, hx, he);
+    else if (wr == 0 || !hasR)
+        halo_blocks<T, K, COMP, 2>(a, rd, w, wr, ws, hasL, hasR, s, e, hx, he);
+    else
+        halo_blocks<T, K, COMP, 1>(a, rd, w, wr, ws, hasL, hasR, s, e, hx, he);
+    // lanes 1..62, lane 0 of the first wave and lane 63 of the last
+    if (rod >= 0 && (lane > 0 || wr == 0) && (lane < kWave - 1 || !hasR)) {
+        store_lane_upto<T, K>(us + g0, g0, rd.n, s);
+        if constexpr (COMP) store_lane_upto<T, K>(ue + g0, g0, rd.n, e);
+    }
+    __syncthreads();   // LDS slots are reused by the next task
+}
+
+// SYNC: 1 = barrier per level, 2 = neighbour flags, 3 = halo lanes (tasks
+// the planner could not give halo lanes use neighbour flags).
+template <typename T, bool COMP, int SYNC>
 __global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
 {
+    constexpr bool NBR = SYNC != 1;
     __shared__ int task_s;
+    __shared__ T hx[SYNC == 3 ? 2 * kWaves * 2 * kMaxBatchK : 1];
+    __shared__ T he[SYNC == 3 && COMP ? 2 * kWaves * 2 * kMaxBatchK : 1];
     for (;;) {
         if (threadIdx.x == 0)
             task_s = atomicAdd(a.counter, 1);
@@ -200,6 +364,19 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
         if (task >= a.ntasks)
             break;
         const BatchTask &tk = a.tasks[task];
+        if (SYNC == 3 && tk.halo) {
+            switch (tk.k) {
+            case 4: run_task_halo<T, 4, COMP>(a, tk, hx, he); break;
+            case 8: run_task_halo<T, 8, COMP>(a, tk, hx, he); break;
+            case 16: run_task_halo<T, 16, COMP>(a, tk, hx, he); break;
+            case 32: run_task_halo<T, 32, COMP>(a, tk, hx, he); break;
+            case 64:
+                if constexpr (sizeof(T) == 4 && !COMP) run_task_halo<T, 64, COMP>(a, tk, hx, he);
+                break;
+            default: break;
+            }
+            continue;
+        }
         switch (tk.k) {
         case 4: run_task<T, 4, COMP, NBR>(a, tk); break;
         case 8: run_task<T, 8, COMP, NBR>(a, tk); break;
@@ -222,11 +399,13 @@ hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stre
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, a.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define GE_BK(T, C)                                                                         \
-    if (a.sync == 2)                                                                         \
-        hipLaunchKernelGGL((batch_kernel<T, C, true>), dim3(grid), dim3(kThreads), 0, stream, a); \
-    else                                                                                     \
-        hipLaunchKernelGGL((batch_kernel<T, C, false>), dim3(grid), dim3(kThreads), 0, stream, a);
+#define GE_BK(T, C)                                                                          \
+    if (a.sync == 3)                                                                          \
+        hipLaunchKernelGGL((batch_kernel<T, C, 3>), dim3(grid), dim3(kThreads), 0, stream, a);   \
+    else if (a.sync == 2)                                                                     \
+        hipLaunchKernelGGL((batch_kernel<T, C, 2>), dim3(grid), dim3(kThreads), 0, stream, a);   \
+    else                                                                                      \
+        hipLaunchKernelGGL((batch_kernel<T, C, 1>), dim3(grid), dim3(kThreads), 0, stream, a);
     switch (prec) {
     case kFP64:
         GE_BK(double, false)

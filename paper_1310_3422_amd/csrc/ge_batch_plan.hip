@@ -54,27 +54,28 @@ int k_index(int k)
 // Default model (per-level microseconds of a 16-wave task), from
 // measurements of the batch kernel on MI355X; used until the device has
 // been tuned.  VALU work grows with K; the constant covers the barrier and
-// the LDS exchange.
-CostModel default_model(int prec)
+// the LDS exchange, which halo-lane tasks pay once every K-1 levels.
+CostModel default_model(int prec, int sync)
 {
     CostModel m;
     const double per_k = prec == ge::kFP32 ? 0.0105 : (prec == ge::kFP64 ? 0.0135 : 0.0215);
     for (int i = 0; i < kNK; ++i) {
-        m.k[i].base = 0.25 + per_k * kKs[i];
+        m.k[i].base = (sync == 3 ? 0.25 / (kKs[i] - 1) : 0.25) + per_k * kKs[i];
         m.k[i].wall = 0.05 + 0.002 * kKs[i];
     }
     return m;
 }
 
-std::string device_key(int prec)
+std::string device_key(int prec, int sync)
 {
     int dev = 0;
     (void)hipGetDevice(&dev);
     hipDeviceProp_t prop;
+    const std::string tail = "/" + std::to_string(prec) + "/s" + std::to_string(sync);
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return "unknown/" + std::to_string(prec);
+        return "unknown" + tail;
     return std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) +
-           "cu/" + std::to_string(prec);
+           "cu" + tail;
 }
 
 std::string cache_path()
@@ -129,6 +130,21 @@ void save_cache_locked()
 
 int waves_for(int64_t n, int k) { return (int)((n + 64 * k - 1) / (64 * k)); }
 
+// Waves of a rod at k points per lane, and whether it runs as a halo-lane
+// task (halo mode, and the overlapping waves fit the workgroup).
+int rod_waves(int64_t n, int k, bool halo_mode, int *halo)
+{
+    if (halo_mode) {
+        const int w = ge::halo_waves(n, k);
+        if (w <= kBatchWaves) {
+            *halo = 1;
+            return w;
+        }
+    }
+    *halo = 0;
+    return waves_for(n, k);
+}
+
 struct Plan {
     std::vector<int> rod_k;
     std::vector<BatchTask> tasks;
@@ -141,7 +157,7 @@ struct Plan {
 // per-level cost, weighted by the share of the workgroup it occupies, is
 // lowest.  All choices give bit-identical results; only the time differs.
 Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int64_t nsteps,
-               int grid)
+               int grid, bool halo_mode)
 {
     const int nr = (int)n.size();
     const int kmax = ge::batch_max_k(prec);
@@ -151,7 +167,7 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
 
     Plan P;
     P.rod_k.assign(nr, 0);
-    struct Bin { int k; int used; int nwall; };
+    struct Bin { int k; int halo; int used; int nwall; };
     std::vector<Bin> bins;
     std::vector<std::vector<int>> members;
     auto task_cost = [&](int k, int nwall) {
@@ -160,15 +176,16 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
     };
     for (int r : order) {
         int best_bin = -1, best_left = 1 << 30;
-        int best_k = 0;
+        int best_k = 0, best_h = 0;
         double best_new = 1e300;
         for (int ki = 0; ki < kNK; ++ki) {
             const int k = kKs[ki];
             if (k > kmax) continue;
-            const int w = waves_for(n[r], k);
+            int h = 0;
+            const int w = rod_waves(n[r], k, halo_mode, &h);
             if (w > kBatchWaves) continue;
             for (size_t b = 0; b < bins.size(); ++b) {
-                if (bins[b].k != k) continue;
+                if (bins[b].k != k || bins[b].halo != h) continue;
                 const int left = kBatchWaves - bins[b].used - w;
                 if (left >= 0 && left < best_left) {
                     best_left = left;
@@ -179,15 +196,17 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
             if (c < best_new) {
                 best_new = c;
                 best_k = k;
+                best_h = h;
             }
         }
         if (best_bin < 0) {
-            bins.push_back(Bin{best_k, 0, 0});
+            bins.push_back(Bin{best_k, best_h, 0, 0});
             members.emplace_back();
             best_bin = (int)bins.size() - 1;
         }
         Bin &b = bins[best_bin];
-        const int w = waves_for(n[r], b.k);
+        int hb = 0;
+        const int w = rod_waves(n[r], b.k, halo_mode, &hb);
         b.used += w;
         b.nwall += std::min(w, 2);
         members[best_bin].push_back(r);
@@ -204,9 +223,11 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
         BatchTask t;
         memset(&t, 0, sizeof t);
         t.k = bins[bi].k;
+        t.halo = bins[bi].halo;
         int w = 0;
         for (int r : members[bi]) {
-            const int nw = waves_for(n[r], t.k);
+            int hb = 0;
+            const int nw = rod_waves(n[r], t.k, halo_mode, &hb);
             for (int j = 0; j < nw; ++j) {
                 t.wave_rod[w] = r;
                 t.wave_idx[w] = j;
@@ -241,7 +262,7 @@ int device_grid()
 
 struct ge_batch_s {
     int prec;
-    int sync;               // 1: barrier per level, 2: neighbour flags
+    int sync;               // 1: barrier per level, 2: neighbour flags, 3: halo lanes
     int64_t nrods;
     int64_t total;          // offsets[nrods]
     int64_t estride;        // e block offset (FP32C)
@@ -295,14 +316,19 @@ void free_batch(ge_batch_s *b)
     delete b;
 }
 
-// Time one run of the batch kernel on a synthetic batch whose tasks are all
-// K-point-per-lane tasks; returns microseconds per level per task.
-double time_tasks(int prec, int k, bool walls, int grid, void *u, size_t ubytes, int *counter,
-                  BatchRod *d_rods, BatchTask *d_tasks, int nsteps, hipStream_t st)
+// Time one run of the batch kernel (synchronisation mode `sync`) on a
+// synthetic batch whose tasks are all K-point-per-lane tasks; returns
+// microseconds per level per task.
+double time_tasks(int prec, int sync, int k, bool walls, int grid, void *u, size_t ubytes,
+                  int *counter, BatchRod *d_rods, BatchTask *d_tasks, int nsteps, hipStream_t st)
 {
     const int ntasks = 2 * grid;
     const int rods_per_task = walls ? kBatchWaves : 1;
-    const int64_t rod_n = walls ? (int64_t)64 * k - 1 : (int64_t)64 * k * kBatchWaves - 1;
+    const bool halo = sync == 3;
+    // rods of one wave each, or one rod over all 16 waves
+    const int64_t rod_n = walls ? (int64_t)64 * k - 1
+                                : (halo ? (int64_t)64 * k + (int64_t)(kBatchWaves - 1) * 62 * k - 1
+                                        : (int64_t)64 * k * kBatchWaves - 1);
     std::vector<BatchRod> rods(ntasks * rods_per_task);
     std::vector<BatchTask> tasks(ntasks);
     const int esz = prec == ge::kFP64 ? 8 : 4;
@@ -314,6 +340,7 @@ double time_tasks(int prec, int k, bool walls, int grid, void *u, size_t ubytes,
     for (int t = 0; t < ntasks; ++t) {
         memset(&tasks[t], 0, sizeof(BatchTask));
         tasks[t].k = k;
+        tasks[t].halo = halo ? 1 : 0;
         for (int w = 0; w < kBatchWaves; ++w) {
             tasks[t].wave_rod[w] = walls ? t * rods_per_task + w : t;
             tasks[t].wave_idx[w] = walls ? 0 : w;
@@ -333,6 +360,7 @@ double time_tasks(int prec, int k, bool walls, int grid, void *u, size_t ubytes,
     a.step0 = 0;
     a.nsteps = nsteps;
     a.ntasks = ntasks;
+    a.sync = sync;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -356,7 +384,7 @@ double time_tasks(int prec, int k, bool walls, int grid, void *u, size_t ubytes,
     return best * 1e3 / (2.0 * nsteps);
 }
 
-ge_status tune_device(int prec, CostModel &m)
+ge_status tune_device(int prec, int sync, CostModel &m)
 {
     const int grid = device_grid();
     const int kmax = ge::batch_max_k(prec);
@@ -383,10 +411,10 @@ ge_status tune_device(int prec, CostModel &m)
                 m.k[i].wall = 0;
                 continue;
             }
-            const double base = time_tasks(prec, kKs[i], false, grid, u, ubytes, counter, d_rods,
-                                           d_tasks, nsteps, st);
-            const double all = time_tasks(prec, kKs[i], true, grid, u, ubytes, counter, d_rods,
-                                          d_tasks, nsteps, st);
+            const double base = time_tasks(prec, sync, kKs[i], false, grid, u, ubytes, counter,
+                                           d_rods, d_tasks, nsteps, st);
+            const double all = time_tasks(prec, sync, kKs[i], true, grid, u, ubytes, counter,
+                                          d_rods, d_tasks, nsteps, st);
             if (base <= 0 || all <= 0) {
                 rc = fail(GE_ERR_HIP, "ge_batch_plan: tuning run failed");
                 break;
@@ -425,9 +453,13 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
         return fail(GE_ERR_INVALID, "ge_batch_plan: a rod table pointer is NULL");
     if (d->precision < GE_FP64 || d->precision > GE_FP32_COMP)
         return fail(GE_ERR_INVALID, "ge_batch_plan: unknown precision %d", d->precision);
-    if (d->sync < 0 || d->sync > 2)
+    if (d->sync < 0 || d->sync > 3)
         return fail(GE_ERR_INVALID, "ge_batch_plan: sync %d unknown", d->sync);
     const int prec = d->precision;
+    // library choice, measured on the 4096-rod batch: halo lanes for the
+    // FP32 forms; FP64 keeps the per-level exchange (its halo-lane code
+    // needs more registers than a 16-wave workgroup leaves a wave)
+    const int sync = d->sync != 0 ? d->sync : (prec == ge::kFP64 ? 2 : 3);
     const int64_t cap = (int64_t)kBatchWaves * 64 * ge::batch_max_k(prec);
     for (int64_t i = 0; i < d->nrods; ++i) {
         if (d->n[i] < 1)
@@ -453,18 +485,18 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache_locked();
-        const std::string key = device_key(prec);
+        const std::string key = device_key(prec, sync);
         auto it = g_tune.find(key);
         if (d->tune || it == g_tune.end() || !it->second.measured) {
             if (d->tune) {
                 CostModel m;
-                ge_status rc = tune_device(prec, m);
+                ge_status rc = tune_device(prec, sync, m);
                 if (rc != GE_OK) return rc;
                 g_tune[key] = m;
                 save_cache_locked();
                 cm = m;
             } else {
-                cm = default_model(prec);
+                cm = default_model(prec, sync);
             }
         } else {
             cm = it->second;
@@ -475,7 +507,7 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
     if (!b)
         return fail(GE_ERR_NOMEM, "ge_batch_plan: out of host memory");
     b->prec = prec;
-    b->sync = d->sync == 0 ? 2 : d->sync;   // neighbour flags: faster in every precision
+    b->sync = sync;
     b->nrods = d->nrods;
     b->total = d->offsets[d->nrods];
     b->estride = prec == ge::kFP32C ? ge::comp_offset(b->total) : 0;
@@ -487,7 +519,7 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
         const ge::SchemeCoef sc = ge::scheme_coef(d->r[i]);
         rods[i] = BatchRod{d->offsets[i], d->n[i], sc.c1, sc.c2, sc.cs, d->g_left[i], d->g_right[i]};
     }
-    Plan P = make_plan(b->n, prec, cm, 1, b->grid);
+    Plan P = make_plan(b->n, prec, cm, 1, b->grid, sync == 3);
     b->rod_k = P.rod_k;
     b->ntasks = (int)P.tasks.size();
     b->est_us = P.est_us;

@@ -308,6 +308,19 @@ template <typename T> struct Coef {
     T e1, e2, es;   // tau(1+r)/(1+2r), tau r/(1+2r), tau/(1+r)
 };
 
+// The coefficients as the level loop reads them.  For FP32 they are moved
+// to vector registers once: measured on MI355X, chains of FP32 VALU
+// instructions with a scalar-register operand issued at half the rate of
+// the same chains with vector-register operands only (no packed forms in
+// either).  FP64 instructions issue at one rate either way.
+template <typename T>
+__device__ __forceinline__ Coef<T> lane_coef(Coef<T> c)
+{
+    if constexpr (sizeof(T) == 4)
+        asm("" : "+v"(c.c1), "+v"(c.c2), "+v"(c.cs), "+v"(c.e1), "+v"(c.e2), "+v"(c.es));
+    return c;
+}
+
 // What a level needs to know about the left wall, seen from one lane (the
 // right wall, at a data-dependent element, is handled by right_lone /
 // put_at around the level).

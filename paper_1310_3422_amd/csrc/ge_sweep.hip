@@ -97,7 +97,7 @@ __device__ __forceinline__ void sweep_tile(const TileArgs &a, int64_t t, int64_t
     if (own_L) accL = a.flux[0];
     if (own_R) accR = a.flux[1];
 
-    const Coef<T> cf{(T)a.c1, (T)a.c2, (T)a.cs, (T)a.e1, (T)a.e2, (T)a.es};
+    const Coef<T> cf = lane_coef(Coef<T>{(T)a.c1, (T)a.c2, (T)a.cs, (T)a.e1, (T)a.e2, (T)a.es});
     FluxTap ft{own_L && tid == 0, accL, a.tau, a.h, 0.0};
 
     for_levels(a.level0, a.nlev, [&](auto par, int lev) {

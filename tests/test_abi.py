@@ -182,7 +182,7 @@ def _batch_desc(n, offsets, r=None, gl=None, gr=None, precision=1, tune=0, sync=
     (dict(n=[100, 50], offsets=[0, 100, 200], r=[1.0, 0.0]), ge.GE_ERR_INVALID),
     (dict(n=[100, 50], offsets=[0, 100, 200], r=[1.0, float("nan")]), ge.GE_ERR_NONFINITE),
     (dict(n=[70000], offsets=[0, 70000]), ge.GE_ERR_UNSUPPORTED),        # above FP32 on-chip limit
-    (dict(n=[100], offsets=[0, 100], sync=3), ge.GE_ERR_INVALID),
+    (dict(n=[100], offsets=[0, 100], sync=4), ge.GE_ERR_INVALID),
     (dict(n=[100], offsets=[0, 100], sync=-1), ge.GE_ERR_INVALID),
     (dict(n=[40000], offsets=[0, 40000], precision=0), ge.GE_ERR_UNSUPPORTED),
     (dict(n=[100], offsets=[0, 100], precision=9), ge.GE_ERR_INVALID),
@@ -256,3 +256,24 @@ def test_plan_schedule_validation():
             assert lib.ge_plan_schedule(h) == (2 if sched == 2 else 1)
             lib.ge_destroy(h)
     assert lib.ge_plan_schedule(None) == -1
+
+
+@pytest.mark.parametrize("prec,depth,src,want", [
+    (0, 0, False, (32, 1, 96, 2)), (0, 0, True, (16, 1, 64, 1)),
+    (0, 1, False, (2, 1, 1, 1)), (0, 8, True, (4, 1, 8, 1)), (0, 16, False, (8, 1, 16, 1)),
+    (0, 32, True, (16, 1, 32, 1)), (0, 64, False, (32, 1, 64, 2)), (0, 64, True, (16, 1, 64, 1)),
+    (1, 0, False, (32, 1, 96, 2)), (1, 4, False, (4, 1, 4, 1)), (1, 8, False, (8, 1, 8, 1)),
+    (1, 8, True, (4, 1, 8, 1)), (1, 16, True, (16, 1, 16, 1)), (1, 64, True, (16, 1, 64, 1)),
+    (2, 0, False, (16, 4, 128, 1)), (2, 2, False, (4, 1, 2, 1)), (2, 32, True, (8, 4, 32, 1)),
+])
+def test_default_tile_follows_depth_and_source(prec, depth, src, want):
+    """The library's tile, waves, depth and schedule when only the depth (or
+    nothing) is given: narrow rows for shallow launches, wide rows and the
+    persistent schedule for deep ones without a source."""
+    st, h = _plan(n=1 << 24, precision=prec, depth=depth,
+                  src_b=ctypes.c_void_p(0x1000) if src else None)
+    assert st == ge.GE_OK
+    t, d, w, hal = (ctypes.c_int32() for _ in range(4))
+    ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w), ctypes.byref(hal))
+    assert (t.value, w.value, d.value, ge.lib().ge_plan_schedule(h)) == want
+    ge.lib().ge_destroy(h)

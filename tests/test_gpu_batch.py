@@ -37,7 +37,7 @@ def start_rod(rb, i, precision):
     return ge.unpack_batch_rod(u, rb.offsets, rb.n, i, precision)
 
 
-@pytest.mark.parametrize("sync", [1, 2])
+@pytest.mark.parametrize("sync", [1, 2, 3])
 @pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32c"])
 def test_small_batch_parity(precision, sync):
     rb = inputs.rod_batch(seed=11, nrods=48, nmin=1, nmax=20000, align=4)
@@ -52,7 +52,7 @@ def test_small_batch_parity(precision, sync):
         assert rel_l2(g, want) < tol, (i, int(rb.n[i]))
 
 
-@pytest.mark.parametrize("sync", [1, 2])
+@pytest.mark.parametrize("sync", [1, 2, 3])
 @pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32c"])
 def test_batch_matches_single_rod_bitwise(precision, sync):
     rb = inputs.rod_batch(seed=12, nrods=24, nmin=3, nmax=30000, align=4)
@@ -68,6 +68,46 @@ def test_batch_matches_single_rod_bitwise(precision, sync):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(ge.unpack_batch_rod(got, rb.offsets, rb.n, i, precision),
                                       ge.unpack_state(u, n, precision))
+
+
+def _sized_batch(sizes, seed):
+    rng = np.random.default_rng(seed)
+    n = np.array(sizes, dtype=np.int64)
+    padded = (n + 3) // 4 * 4
+    offsets = np.zeros(n.size + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(padded)
+    u0 = np.zeros(int(offsets[-1]))
+    for i, m in enumerate(sizes):
+        u0[offsets[i]:offsets[i] + m] = inputs.sine_modes(int(m), rng.standard_normal(16)) + \
+            0.01 * rng.standard_normal(m)
+    return inputs.RodBatch(n=n, r=rng.uniform(0.25, 4.0, n.size), g_left=rng.uniform(-1, 1, n.size),
+                           g_right=rng.uniform(-1, 1, n.size), offsets=offsets, u0=u0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "fp32c"])
+def test_halo_lane_tasks_at_wave_boundaries(precision):
+    """Rods whose lengths sit at the edges of the overlapping-wave layout
+    (one wave of 64k points, 62k more per further wave, the largest rod that
+    fits 16 waves and the next one, which falls back to the per-level
+    exchange) for k = 4..64: bit-identical to the single-rod sweep over a
+    level count that is no multiple of any block length (k - 1)."""
+    cap = 65536 if precision == "fp32" else 32768
+    sizes = [1, 2, 3, 5, 6]
+    for k in (4, 8, 16, 32, 64):
+        for m in (64 * k, 64 * k + 62 * k, 64 * k + 15 * 62 * k):
+            sizes += [m - 1, m, m + 1]
+    sizes = sorted(set(x for x in sizes if x <= cap)) + [cap]
+    rb = _sized_batch(sizes, seed=21)
+    nsteps = 131
+    b, got = run_batch(rb, precision, nsteps, step0=1, sync=3)
+    for i in range(rb.nrods):
+        n = int(rb.n[i])
+        plan = ge.Plan(n, rb.r[i], precision, g_left=rb.g_left[i], g_right=rb.g_right[i])
+        u = ge.pack_state(start_rod(rb, i, precision), precision)
+        plan.step_n(u, 1, nsteps)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ge.unpack_batch_rod(got, rb.offsets, rb.n, i, precision),
+                                      ge.unpack_state(u, n, precision), err_msg=f"rod {i}, n={n}")
 
 
 def test_graph_replays_match_eager_result():

@@ -234,7 +234,8 @@ ge_status ge_solve_batch(ge_batch_t batch, void *u, void *workspace,
  * with s the RMS of the rod's second differences.  Layers (channels last,
  * bfloat16 activations and weights, FP32 accumulation on the matrix cores):
  * conv 2->64 + GELU; four residual layers h += GELU(conv 64->64); conv
- * 64->1; kernel width 5, zero padding, exact-erf GELU.  Inputs: the second
+ * 64->1; kernel width 5, tap spacings 1, 2, 4, 8, 16, 1, zero padding, GELU
+ * in its tanh form (z/2)(1 + tanh(sqrt(2/pi)(z + 0.044715 z^3))).  Inputs: the second
  * difference of u divided by s, and r mapped from [0.5, 2] to [-1, 1].
  * Training minimises the mean squared error against the normalised
  * increment (u(m + 64) - u(m)) / (64 r s) of the GE sweep, with Adam on

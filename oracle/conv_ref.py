@@ -13,7 +13,9 @@ over the n points of a rod, channels-last tensors x[b, w, c].
 
     conv_l(x, W)[b, w, o] = sum_{k=0..4} sum_i W[k, o, i] x[b, w + (k - 2) d_l, i],
     dilations d = (1, 2, 4, 8, 16, 1), x = 0 outside the rod (zero padding),
-    gelu(z) = z Phi(z) with the exact normal CDF Phi.  The dilations give a
+    gelu(z) = (z/2) (1 + tanh(c (z + 0.044715 z^3))), c = sqrt(2/pi): the
+    tanh form of z Phi(z) (within 4.8e-4 of it for every z), whose GPU
+    evaluation needs one exponential and one reciprocal.  The dilations give a
     receptive field of +-64 points: 64 levels of the sweep move a point's
     influence about as far (at r = 2 a fifth of the increment caused by a
     point lies more than 13 points away, which a plain kernel-5 stack of six
@@ -53,17 +55,20 @@ def bf16(a):
     return out.astype(np.float64)
 
 
-def _erf(x):
-    return np.vectorize(math.erf, otypes=[np.float64])(x)
+GELU_C = math.sqrt(2.0 / math.pi)
+GELU_A = 0.044715
 
 
 def gelu(z):
-    return 0.5 * z * (1.0 + _erf(z / math.sqrt(2.0)))
+    """(z/2) (1 + tanh(c (z + a z^3)))."""
+    return 0.5 * z * (1.0 + np.tanh(GELU_C * (z + GELU_A * z ** 3)))
 
 
 def gelu_grad(z):
-    phi = np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
-    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * phi
+    """d gelu / dz = (1 + tanh w)/2 + (z/2) (1 - tanh^2 w) c (1 + 3 a z^2),
+    w = c (z + a z^3)."""
+    t = np.tanh(GELU_C * (z + GELU_A * z ** 3))
+    return 0.5 * (1.0 + t) + 0.5 * z * (1.0 - t * t) * GELU_C * (1.0 + 3.0 * GELU_A * z * z)
 
 
 def conv(x, w, d=1):

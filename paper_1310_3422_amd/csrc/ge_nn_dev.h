@@ -19,34 +19,28 @@ constexpr int kTaps = 5;
 __device__ __forceinline__ float bf2f(bf16 v) { return (float)v; }
 __device__ __forceinline__ bf16 f2bf(float v) { return (bf16)v; }   // round to nearest even
 
-// Standard normal distribution at z: Phi(z) from the upper tail
-// Q(x) = 1 - Phi(x), x = |z|, by Abramowitz and Stegun 26.2.17,
-//     Q(x) = phi(x) (b1 t + b2 t^2 + b3 t^3 + b4 t^4 + b5 t^5),  t = 1 / (1 + p x),
-// absolute error below 7.5e-8; branch free, and the negative tail comes out
-// without the cancellation of 1 + erf.  phi is the density.
-struct Normal {
-    float cdf, pdf;
-};
-__device__ __forceinline__ Normal normal_at(float z)
-{
-    const float x = fabsf(z);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.2316419f, x, 1.0f));
-    float poly = fmaf(t, 1.330274429f, -1.821255978f);
-    poly = fmaf(t, poly, 1.781477937f);
-    poly = fmaf(t, poly, -0.356563782f);
-    poly = fmaf(t, poly, 0.319381530f);
-    poly *= t;
-    const float pdf = 0.398942280401432678f * __expf(-0.5f * x * x);
-    const float q = pdf * poly;
-    return Normal{z >= 0.f ? 1.0f - q : q, pdf};
-}
+// GELU in its tanh form, gelu(z) = (z/2) (1 + tanh(c (z + a z^3))),
+// c = sqrt(2/pi), a = 0.044715, evaluated as z sigma(2w) = z / (1 + e^{-2w}),
+// w = c (z + a z^3): one exp2, one reciprocal and four other operations.
+// For z -> -inf the exponential overflows to +inf and the reciprocal gives
+// 0, so no NaN appears.
+constexpr float kGeluE0 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;   // -2c log2(e)
+constexpr float kGeluE2 = kGeluE0 * 0.044715f;
+constexpr float kGeluD0 = 2.0f * 0.7978845608028654f;                          // 2c
+constexpr float kGeluD2 = kGeluD0 * 3.0f * 0.044715f;
 
-// GELU(z) = z Phi(z) and its derivative Phi(z) + z phi(z)
-__device__ __forceinline__ float gelu(float z) { return z * normal_at(z).cdf; }
+// sigma(2w) for the argument z
+__device__ __forceinline__ float gelu_sigma(float z)
+{
+    const float e = __builtin_amdgcn_exp2f(z * fmaf(z * z, kGeluE2, kGeluE0));
+    return __builtin_amdgcn_rcpf(1.0f + e);
+}
+__device__ __forceinline__ float gelu(float z) { return z * gelu_sigma(z); }
+// d gelu / dz = s + z s (1 - s) 2w',  s = sigma(2w), 2w' = 2c (1 + 3 a z^2)
 __device__ __forceinline__ float gelu_grad(float z)
 {
-    const Normal nz = normal_at(z);
-    return nz.cdf + z * nz.pdf;
+    const float sg = gelu_sigma(z);
+    return fmaf(z * sg, (1.0f - sg) * fmaf(z * z, kGeluD2, kGeluD0), sg);
 }
 
 // 16-byte copy between global and LDS

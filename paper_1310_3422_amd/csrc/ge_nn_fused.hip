@@ -139,19 +139,30 @@ __device__ __forceinline__ void gelu_epilogue(bf16 *act, const f32x4 (&acc)[kFMT
         const int q = 16 * (kFMT * wv + m) + r16;          // computed row (position)
         const int w = w0 - kFHalo + q;
         const bool in = w >= 0 && w < W;
+        // whether all 16 rows of the M-tile lie in the rod (wave-uniform)
+        const int wt = w0 - kFHalo + 16 * (kFMT * wv + m);
+        const bool tile_in = wt >= 0 && wt + 15 < W;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             bf16x4 *dst = reinterpret_cast<bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]);
             bf16x4 hv;
             if (RES) hv = *dst;
-            bf16x4 o;
+            f32x4 h;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                float h = gelu(acc[m][n][j] + bl[n][j]);
-                if (RES) h += bf2f(hv[j]);
-                o[j] = in ? f2bf(h) : f2bf(0.f);
+                h[j] = gelu(acc[m][n][j] + bl[n][j]);
+                if (RES) h[j] += bf2f(hv[j]);
             }
-            *dst = o;
+            // two values per conversion instruction (round to nearest even)
+            *dst = __builtin_convertvector(h, bf16x4);
+        }
+        // rows outside the rod back to zero: only in the M-tiles at a rod's
+        // ends (tile_in is wave-uniform), by the lanes that wrote them
+        if (!tile_in && !in) {
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+                *reinterpret_cast<bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]) =
+                    bf16x4{f2bf(0.f), f2bf(0.f), f2bf(0.f), f2bf(0.f)};
         }
         // one M-tile at a time: no hoisting of later tiles' reads, which
         // would crowd out the registers of the weights in flight

@@ -2,6 +2,8 @@
 the convolution against its definition on a delta input, the backward pass
 against central finite differences, and bfloat16 rounding against values
 fixed by the format."""
+import math
+
 import numpy as np
 import pytest
 
@@ -52,13 +54,23 @@ def test_input_and_weight_gradients_are_adjoint(d):
 
 
 def test_gelu_values():
-    z = np.array([-2.0, 0.0, 1.0])
-    # z * Phi(z), Phi from the error function
-    np.testing.assert_allclose(cr.gelu(z), [-0.04550026389635842, 0.0, 0.8413447460685429],
-                               rtol=1e-14)
+    """The tanh form against z Phi(z) with Phi from the error function: the
+    form's known largest gap, about 4.7e-4 near |z| = 2.7 (a dropped cubic
+    term gives 2e-2, a wrong scale more), odd-symmetric gaps, the limits, and
+    the derivative against central differences."""
+    z = np.linspace(-10.0, 10.0, 200001)
+    exact = 0.5 * z * (1.0 + np.vectorize(math.erf)(z / math.sqrt(2.0)))
+    gap = np.abs(cr.gelu(z) - exact)
+    assert 4.6e-4 < gap.max() < 4.8e-4
+    assert 2.6 < abs(z[np.argmax(gap)]) < 2.8
+    # gelu(z) - gelu(-z) = z for both (Phi(z) + Phi(-z) = 1)
+    np.testing.assert_allclose(cr.gelu(z) - cr.gelu(-z), z, atol=1e-14)
+    assert cr.gelu(np.array([0.0]))[0] == 0.0
+    np.testing.assert_allclose(cr.gelu(np.array([-40.0, 40.0])), [0.0, 40.0], atol=1e-300)
+    zs = np.array([-2.0, -0.3, 0.0, 1.0, 2.7])
     eps = 1e-6
-    fd = (cr.gelu(z + eps) - cr.gelu(z - eps)) / (2 * eps)
-    np.testing.assert_allclose(cr.gelu_grad(z), fd, rtol=1e-8)
+    fd = (cr.gelu(zs + eps) - cr.gelu(zs - eps)) / (2 * eps)
+    np.testing.assert_allclose(cr.gelu_grad(zs), fd, rtol=1e-8, atol=1e-10)
 
 
 def _small_params(seed):

@@ -188,9 +188,10 @@ typedef struct {
                              /* workgroup barrier, 2 = every level, each wave */
                              /* waiting for its two neighbours only (level    */
                              /* flags in LDS), 3 = neighbouring waves overlap */
-                             /* by one lane, refreshed at a barrier every K-1 */
-                             /* levels (rods whose overlapping waves do not   */
-                             /* fit a workgroup fall back to 2)               */
+                             /* by a lane or more, refreshed at a barrier     */
+                             /* every K-1 levels (the default; rods of one    */
+                             /* wave and rods whose overlapping waves do not  */
+                             /* fit a workgroup use 2 in the same launch)     */
 } ge_batch_desc;
 
 /* Create a batch plan: choose points per lane for every rod, bundle rods

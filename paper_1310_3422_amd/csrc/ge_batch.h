@@ -45,11 +45,40 @@ struct BatchArgs {
 // Waves a rod of n points needs at k points per lane when neighbouring
 // waves overlap by one lane (halo tasks): 64k points for the first wave and
 // 62k new points for each further one.
-inline int halo_waves(int64_t n, int k)
+__host__ __device__ inline int halo_waves(int64_t n, int k)
 {
     const int64_t w = 64 * (int64_t)k, c = 62 * (int64_t)k;
     return n <= w ? 1 : (int)(1 + (n - w + c - 1) / c);
 }
+
+// Where the waves of a halo task's rod start: wave j at 62 k j, except the
+// last, which ends at the right wall node rounded up to a 16-byte boundary
+// (so its start stays even and aligned).  `fits`: the rod has two or more
+// waves and the last window does not reach into its neighbour's duplicated
+// lane; only such rods go to halo tasks.
+struct HaloLayout {
+    int64_t n;
+    int k, m;
+    int64_t last;
+    bool fits;
+    __host__ __device__ HaloLayout(int64_t n_, int k_) : n(n_), k(k_), m(halo_waves(n_, k_))
+    {
+        last = (int64_t)(m - 1) * 62 * k;
+        fits = false;
+        if (m >= 2) {
+            const int64_t r = (n - 64 * (int64_t)k + 3) / 4 * 4;
+            const int64_t need = m == 2 ? 0 : (int64_t)(m - 2) * 62 * k + k;
+            if (r >= need) {
+                last = r;
+                fits = true;
+            }
+        }
+    }
+    __host__ __device__ int64_t start(int j) const
+    {
+        return j == m - 1 ? last : (int64_t)j * 62 * k;
+    }
+};
 
 hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream);
 int batch_max_k(int prec);

@@ -189,16 +189,28 @@ __device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk
 
 // ---- halo-lane tasks ------------------------------------------------------
 // Wave j of a rod holds the window [62 k j, 62 k j + 64 k): its lanes 0 and
-// 63 duplicate the neighbouring waves' lanes 62 and 1.  A level-(m+1) value
-// depends on level-m values at most two places away, and a value that is
-// wrong at an open window edge spreads inward by at most one point per
-// level after the first, so after the duplicated lanes are refreshed the
-// wave can advance k-1 levels on its own (wave-edge values entering as zero)
-// and lanes 1..62 stay exact.  The refresh goes through LDS with one
-// workgroup barrier every k-1 levels instead of an exchange every level.
-// Walls stay exact at the rod's ends: the first wave has no left duplicate
-// and the last holds the right wall, as in the per-level form.
+// 63 duplicate values of the neighbouring waves (their lanes 62 and 1).  A
+// level-(m+1) value depends on level-m values at most two places away, and a
+// value that is wrong at an open window edge spreads inward by at most one
+// point per level after the first, so after the duplicated lanes are
+// refreshed the wave can advance k-1 levels on its own (wave-edge values
+// entering as zero) and lanes 1..62 stay exact.  The refresh goes through
+// LDS with one workgroup barrier every k-1 levels instead of an exchange
+// every level.
+//
+// Walls stay exact at the rod's ends.  The first wave starts at the left
+// wall, which enters as the fill of its lane 0.  The last wave is placed so
+// that the right wall node falls at (or within three points of) the end of
+// its window, at a fixed element of lane 63: that costs a select or two per
+// level, where a wall node at a data-dependent element costs a branch tree
+// per access.  It then overlaps its neighbour by more than one lane, and the
+// refresh copies values by position: the writer's lanes covering the
+// positions store them to LDS, the reader takes k values at the offset.
+// When the last window would reach into its neighbour's duplicated lane (a
+// 1-in-62 case), or the rod has one wave, the wall node stays where the
+// regular placement puts it.
 constexpr int kMaxBatchK = 64;
+constexpr int kSlot = 2 * kMaxBatchK;    // values per exchange slot (two lanes)
 
 template <typename T, int K, bool COMP, bool WALL>
 __device__ __forceinline__ void rod_block(const BatchRod &rd, int wr, int64_t ws, T (&s)[K],
@@ -253,50 +265,141 @@ __device__ __forceinline__ void rod_block(const BatchRod &rd, int wr, int64_t ws
     });
 }
 
+// The last wave of a rod with its window ending RQ points (0..3) past the
+// right wall node: the node is element K - RQ of lane 63 (RQ = 0: just
+// beyond the window, the fill of lane 63), the lone point beside it element
+// K - 1 - RQ.  Both indices are compile-time constants.  The window start
+// is even, so the local pairing is the global one.
+template <typename T, int K, bool COMP, int RQ>
+__device__ __forceinline__ void rod_block_right(const BatchRod &rd, T (&s)[K], T (&e)[K],
+                                                int64_t level0, int nlev)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t n = rd.n;
+    T gr_hi, gr_lo;
+    split_wall<T, COMP>(rd.gr, gr_hi, gr_lo);
+    const Coef<T> cf = lane_coef(Coef<T>{(T)rd.c1, (T)rd.c2, (T)rd.cs, T(0), T(0), T(0)});
+    const T b0[K] = {};
+    FluxTap ft{false, 0.0, 0.0, 1.0, 0.0};
+    const WallLevel<T> wlv{false, T(0)};
+    constexpr int kS = K - 1 - RQ;
+    const bool lone_odd = ((n - 1) & 1) == 0;   // the lone point exists at even global parity
+    for_levels(level0, nlev, [&](auto par, int) {
+        constexpr int p = decltype(par)::value;
+        if constexpr (RQ > 0) {
+            put_at<T, K>(s, K - RQ, lane == kWave - 1, gr_hi);
+            if constexpr (COMP) put_at<T, K>(e, K - RQ, lane == kWave - 1, gr_lo);
+        }
+        const T xr = RQ == 0 ? gr_hi : T(0), yr = (RQ == 0 && COMP) ? gr_lo : T(0);
+        const bool singR = lone_odd == (p == 0);
+        Lone<T> lone{T(0), T(0)};
+        if (singR)
+            lone = right_lone<T, K, COMP, false>(s, e, b0, kS, T(0), T(0), gr_hi, gr_lo, T(0), cf,
+                                                 T(0));
+        ge_level<T, K, COMP, false, false, p, false>(s, e, b0, T(0), T(0), T(0), T(0), xr, T(0),
+                                                     T(0), T(0), yr, T(0), cf, T(0), wlv, ft);
+        if (singR) {
+            put_at<T, K>(s, kS, lane == kWave - 1, lone.s);
+            if constexpr (COMP) put_at<T, K>(e, kS, lane == kWave - 1, lone.e);
+        }
+    });
+}
+
+// The first wave of a rod that spans several: the left wall enters as the
+// fill of lane 0 and the lone point beside it is element 0 of lane 0; the
+// right edge is open.
+template <typename T, int K, bool COMP>
+__device__ __forceinline__ void rod_block_left(const BatchRod &rd, T (&s)[K], T (&e)[K],
+                                               int64_t level0, int nlev)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    T gl_hi, gl_lo;
+    split_wall<T, COMP>(rd.gl, gl_hi, gl_lo);
+    const Coef<T> cf = lane_coef(Coef<T>{(T)rd.c1, (T)rd.c2, (T)rd.cs, T(0), T(0), T(0)});
+    const T b0[K] = {};
+    FluxTap ft{false, 0.0, 0.0, 1.0, 0.0};
+    for_levels(level0, nlev, [&](auto par, int) {
+        constexpr int p = decltype(par)::value;
+        const WallLevel<T> wlv{p == 1 && lane == 0, T(0)};
+        ge_level<T, K, COMP, false, true, p, false>(s, e, b0, T(0), T(0), gl_hi, T(0), T(0), T(0),
+                                                    COMP ? gl_lo : T(0), T(0), T(0), T(0), cf,
+                                                    T(0), wlv, ft);
+    });
+}
+
 // The levels of a halo-lane task for one wave, in blocks of K-1 levels with
 // the duplicated lanes refreshed between blocks.  hx: [2 buffers][waves]
-// [2 slots][kMaxBatchK] values of s (he: of e, for the pair); slot 0
-// carries lane 62 to the right neighbour, slot 1 lane 1 to the left one.
-// MODE: 0 = a wave without a rod (it only passes the barriers), 1 = both
-// window edges open, 2 = a wave holding a wall.  Every wave of the
-// workgroup passes the same barriers (all rods of a task share K and the
-// level count); the mode is chosen once per wave, outside the block loop,
-// so each wave runs one instantiation of the level code.
+// [2 slots][kSlot] values of s (he: of e, for the pair).  Slot 0 of wave w
+// carries the positions its right neighbour duplicates in lane 0, slot 1
+// those its left neighbour duplicates in lane 63; a slot holds the two lanes
+// that cover them, and the reader starts at the positions' offset within
+// the first.  aL / aR: window start of this wave minus the left neighbour's,
+// and of the right neighbour minus this wave's.  MODE: 0 = a wave without a
+// rod (it only passes the barriers), 1 = both window edges open, 2 = a wave
+// holding a wall at its regular place, 3 + RQ = the last wave ending RQ
+// points past the right wall node, 7 = the first wave of several.  Every wave of the workgroup passes the
+// same barriers (all rods of a task share K and the level count); the mode
+// is chosen once per wave, outside the block loop, so each wave runs one
+// instantiation of the level code.
 template <typename T, int K, bool COMP, int MODE>
 __device__ __forceinline__ void halo_blocks(const BatchArgs &a, const BatchRod &rd, int w, int wr,
-                                            int64_t ws, bool hasL, bool hasR, T (&s)[K],
-                                            T (&e)[K], T *hx, T *he)
+                                            int64_t ws, int aL, int aR, bool hasL, bool hasR,
+                                            T (&s)[K], T (&e)[K], T *hx, T *he)
 {
     const int lane = threadIdx.x & (kWave - 1);
     auto slot = [&](int buf, int wave, int which) {
-        return ((buf * kWaves + wave) * 2 + which) * kMaxBatchK;
+        return ((buf * kWaves + wave) * 2 + which) * kSlot;
     };
+    // lanes that write slot 0 (positions [aR, aR + K) of this window) and
+    // slot 1 (positions [63K - aL, 64K - aL))
+    const int l0 = aR / K, r0 = aR % K;
+    const int bL = 63 * K - aL, l1 = bL / K, r1 = bL % K;
     int64_t done = 0;
     for (int blk = 0;; ++blk) {
         const int nb = (int)((a.nsteps - done) < (K - 1) ? (a.nsteps - done) : (K - 1));
-        if constexpr (MODE != 0)
-            rod_block<T, K, COMP, MODE == 2>(rd, wr, ws, s, e, a.step0 + done, nb);
+        if constexpr (MODE == 1)
+            rod_block<T, K, COMP, false>(rd, wr, ws, s, e, a.step0 + done, nb);
+        else if constexpr (MODE >= 3 && MODE <= 6)
+            rod_block_right<T, K, COMP, MODE - 3>(rd, s, e, a.step0 + done, nb);
+        else if constexpr (MODE == 7)
+            rod_block_left<T, K, COMP>(rd, s, e, a.step0 + done, nb);
         done += nb;
         if (done >= a.nsteps)
             break;
         const int pb = blk & 1;
-        if (MODE != 0 && (lane == kWave - 2 || lane == 1)) {
-            const int o = slot(pb, w, lane == 1 ? 1 : 0);
+        if constexpr (MODE != 0) {
+            if (hasR && (lane == l0 || (r0 != 0 && lane == l0 + 1))) {
+                const int o = slot(pb, w, 0) + (lane - l0) * K;
 #pragma unroll
-            for (int j = 0; j < K; ++j) hx[o + j] = s[j];
-            if constexpr (COMP) {
+                for (int j = 0; j < K; ++j) hx[o + j] = s[j];
+                if constexpr (COMP) {
 #pragma unroll
-                for (int j = 0; j < K; ++j) he[o + j] = e[j];
+                    for (int j = 0; j < K; ++j) he[o + j] = e[j];
+                }
+            }
+            if (hasL && (lane == l1 || (r1 != 0 && lane == l1 + 1))) {
+                const int o = slot(pb, w, 1) + (lane - l1) * K;
+#pragma unroll
+                for (int j = 0; j < K; ++j) hx[o + j] = s[j];
+                if constexpr (COMP) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) he[o + j] = e[j];
+                }
             }
         }
         __syncthreads();
-        if (MODE != 0 && ((lane == 0 && hasL) || (lane == kWave - 1 && hasR))) {
-            const int o = lane == 0 ? slot(pb, w - 1, 0) : slot(pb, w + 1, 1);
+        if constexpr (MODE != 0) {
+            if ((lane == 0 && hasL) || (lane == kWave - 1 && hasR)) {
+                // left: the left neighbour's slot 0 at this window's offset in it;
+                // right: the right neighbour's slot 1 at that window's offset
+                const int o = lane == 0 ? slot(pb, w - 1, 0) + aL % K
+                                        : slot(pb, w + 1, 1) + (63 * K - aR) % K;
 #pragma unroll
-            for (int j = 0; j < K; ++j) s[j] = hx[o + j];
-            if constexpr (COMP) {
+                for (int j = 0; j < K; ++j) s[j] = hx[o + j];
+                if constexpr (COMP) {
 #pragma unroll
-                for (int j = 0; j < K; ++j) e[j] = he[o + j];
+                    for (int j = 0; j < K; ++j) e[j] = he[o + j];
+                }
             }
         }
     }
@@ -316,12 +419,27 @@ __device__ __forceinline__ void run_task_halo(const BatchArgs &a, const BatchTas
     T s[K], e[K];
     BatchRod rd{};
     T *us = nullptr, *ue = nullptr;
-    const int64_t ws = (int64_t)wr * 62 * K;          // window start (even)
-    const int64_t g0 = ws + (int64_t)lane * K;
+    int64_t ws = 0, lo = 0;
+    int aL = 62 * K, aR = 62 * K, mode = 0;
     if (rod >= 0) {
         rd = a.rods[rod];
+        const HaloLayout L(rd.n, K);
+        ws = L.start(wr);                           // a multiple of 4
+        if (hasL) aL = (int)(ws - L.start(wr - 1));
+        if (hasR) aR = (int)(L.start(wr + 1) - ws);
+        // the last wave stores only beyond its neighbour's core
+        lo = (wr == L.m - 1 && wr > 0) ? L.start(wr - 1) + 63 * K : 0;
+        // the planner gives halo tasks only rods of two or more waves whose
+        // last window ends at the wall
+        if (!hasR)
+            mode = 3 + (int)(ws + 64 * K - rd.n);   // RQ in 0..3
+        else
+            mode = wr == 0 ? 7 : 1;
         us = static_cast<T *>(a.u) + rd.off;
         ue = static_cast<T *>(a.u) + a.estride + rd.off;
+    }
+    const int64_t g0 = ws + (int64_t)lane * K;
+    if (rod >= 0) {
         load_lane_guarded<T, K>(us + g0, g0, rd.n, s);
         if constexpr (COMP) load_lane_guarded<T, K>(ue + g0, g0, rd.n, e);
     } else {
@@ -332,16 +450,20 @@ __device__ __forceinline__ void run_task_halo(const BatchArgs &a, const BatchTas
 #pragma unroll
         for (int j = 0; j < K; ++j) e[j] = T(0);
     }
-    if (rod < 0)
-        halo_blocks<T, K, COMP, 0>(a, rd, w, wr, ws, hasL, hasR, s, e, hx, he);
-    else if (wr == 0 || !hasR)
-        halo_blocks<T, K, COMP, 2>(a, rd, w, wr, ws, hasL, hasR, s, e, hx, he);
-    else
-        halo_blocks<T, K, COMP, 1>(a, rd, w, wr, ws, hasL, hasR, s, e, hx, he);
-    // lanes 1..62, lane 0 of the first wave and lane 63 of the last
+    switch (__builtin_amdgcn_readfirstlane(mode)) {
+    case 1: halo_blocks<T, K, COMP, 1>(a, rd, w, wr, ws, aL, aR, hasL, hasR, s, e, hx, he); break;
+    case 3: halo_blocks<T, K, COMP, 3>(a, rd, w, wr, ws, aL, aR, hasL, hasR, s, e, hx, he); break;
+    case 4: halo_blocks<T, K, COMP, 4>(a, rd, w, wr, ws, aL, aR, hasL, hasR, s, e, hx, he); break;
+    case 5: halo_blocks<T, K, COMP, 5>(a, rd, w, wr, ws, aL, aR, hasL, hasR, s, e, hx, he); break;
+    case 6: halo_blocks<T, K, COMP, 6>(a, rd, w, wr, ws, aL, aR, hasL, hasR, s, e, hx, he); break;
+    case 7: halo_blocks<T, K, COMP, 7>(a, rd, w, wr, ws, aL, aR, hasL, hasR, s, e, hx, he); break;
+    default: halo_blocks<T, K, COMP, 0>(a, rd, w, wr, ws, aL, aR, hasL, hasR, s, e, hx, he); break;
+    }
+    // lanes 1..62, lane 0 of the first wave and lane 63 of the last (the last
+    // wave from its neighbour's core end on)
     if (rod >= 0 && (lane > 0 || wr == 0) && (lane < kWave - 1 || !hasR)) {
-        store_lane_upto<T, K>(us + g0, g0, rd.n, s);
-        if constexpr (COMP) store_lane_upto<T, K>(ue + g0, g0, rd.n, e);
+        store_lane_range<T, K>(us + g0, g0, lo, rd.n, s);
+        if constexpr (COMP) store_lane_range<T, K>(ue + g0, g0, lo, rd.n, e);
     }
     __syncthreads();   // LDS slots are reused by the next task
 }
@@ -353,8 +475,8 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
 {
     constexpr bool NBR = SYNC != 1;
     __shared__ int task_s;
-    __shared__ T hx[SYNC == 3 ? 2 * kWaves * 2 * kMaxBatchK : 1];
-    __shared__ T he[SYNC == 3 && COMP ? 2 * kWaves * 2 * kMaxBatchK : 1];
+    __shared__ T hx[SYNC == 3 ? 2 * kWaves * 2 * kSlot : 1];
+    __shared__ T he[SYNC == 3 && COMP ? 2 * kWaves * 2 * kSlot : 1];
     for (;;) {
         if (threadIdx.x == 0)
             task_s = atomicAdd(a.counter, 1);

@@ -131,14 +131,15 @@ void save_cache_locked()
 int waves_for(int64_t n, int k) { return (int)((n + 64 * k - 1) / (64 * k)); }
 
 // Waves of a rod at k points per lane, and whether it runs as a halo-lane
-// task (halo mode, and the overlapping waves fit the workgroup).
+// task (halo mode, two or more overlapping waves that fit the workgroup, and
+// a last window that can end at the wall).
 int rod_waves(int64_t n, int k, bool halo_mode, int *halo)
 {
     if (halo_mode) {
-        const int w = ge::halo_waves(n, k);
-        if (w <= kBatchWaves) {
+        const ge::HaloLayout L(n, k);
+        if (L.fits && L.m <= kBatchWaves) {
             *halo = 1;
-            return w;
+            return L.m;
         }
     }
     *halo = 0;
@@ -340,7 +341,7 @@ double time_tasks(int prec, int sync, int k, bool walls, int grid, void *u, size
     for (int t = 0; t < ntasks; ++t) {
         memset(&tasks[t], 0, sizeof(BatchTask));
         tasks[t].k = k;
-        tasks[t].halo = halo ? 1 : 0;
+        tasks[t].halo = (halo && !walls) ? 1 : 0;   // one-wave rods never run as halo tasks
         for (int w = 0; w < kBatchWaves; ++w) {
             tasks[t].wave_rod[w] = walls ? t * rods_per_task + w : t;
             tasks[t].wave_idx[w] = walls ? 0 : w;
@@ -456,10 +457,9 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
     if (d->sync < 0 || d->sync > 3)
         return fail(GE_ERR_INVALID, "ge_batch_plan: sync %d unknown", d->sync);
     const int prec = d->precision;
-    // library choice, measured on the 4096-rod batch: halo lanes for the
-    // FP32 forms; FP64 keeps the per-level exchange (its halo-lane code
-    // needs more registers than a 16-wave workgroup leaves a wave)
-    const int sync = d->sync != 0 ? d->sync : (prec == ge::kFP64 ? 2 : 3);
+    // library choice, measured on the 4096-rod batch: halo lanes (+23% FP32,
+    // +21% pair, +26% FP64 over neighbour flags)
+    const int sync = d->sync != 0 ? d->sync : 3;
     const int64_t cap = (int64_t)kBatchWaves * 64 * ge::batch_max_k(prec);
     for (int64_t i = 0; i < d->nrods; ++i) {
         if (d->n[i] < 1)

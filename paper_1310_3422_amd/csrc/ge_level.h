@@ -228,6 +228,37 @@ __device__ __forceinline__ void store_lane_upto(T *__restrict__ p, int64_t g0, i
     }
 }
 
+// Store the values whose global index lies in [lo, n): lo is a multiple of
+// the chunk width, so a chunk is wholly below lo or not; the chunk that
+// straddles n goes value by value.
+template <typename T, int K>
+__device__ __forceinline__ void store_lane_range(T *__restrict__ p, int64_t g0, int64_t lo,
+                                                 int64_t n, const T (&v)[K])
+{
+    using V = typename V16<T>::type;
+    constexpr int E = V16<T>::E;
+    V *q = reinterpret_cast<V *>(p);
+#pragma unroll
+    for (int c = 0; c < K / E; ++c) {
+        if (g0 + c * E < lo)
+            continue;
+        if (g0 + (c + 1) * E <= n) {
+            V x;
+            if constexpr (E == 4) {
+                x.x = v[4 * c]; x.y = v[4 * c + 1]; x.z = v[4 * c + 2]; x.w = v[4 * c + 3];
+            } else {
+                x.x = v[2 * c]; x.y = v[2 * c + 1];
+            }
+            q[c] = x;
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i)
+                if (g0 + c * E + i < n)
+                    p[c * E + i] = v[c * E + i];
+        }
+    }
+}
+
 // Access to element k of a lane's register tile for a wave-uniform k, as a
 // switch: one scalar branch tree and a single move per call.  (An equality
 // chain over the tile would be folded into one dynamically indexed access,

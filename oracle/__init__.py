@@ -6,6 +6,9 @@ only tests/, the smoke check and the benchmark's CPU-baseline leg use it.
 * ``step_n``: the GE scheme of Section 2 (Eq. (1)-(4), two-point groups,
   alternating grouping) in plain C, FP64 or x87 extended precision
   (``ge_ref.c``).
+* ``sdc_step_n``: the same scheme with sub-domains of k nodes (Section 2's
+  complementary scheme: Eq. (3)/(4) where sub-domains meet, Saul'yev
+  sweeps Eq. (1)/(2) inside them), FP64 (``sdc_ref.c``).
 * ``conv_ref``: the FP64 forward/backward of the 1D convolutional propagator.
 """
 import ctypes
@@ -24,7 +27,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    src = [os.path.join(_HERE, f) for f in ("ge_ref.c", "ge_ref_core.inc")]
+    src = [os.path.join(_HERE, f) for f in ("ge_ref.c", "ge_ref_core.inc", "sdc_ref.c")]
     if not os.path.exists(_LIB_PATH) or any(
             os.path.getmtime(s) > os.path.getmtime(_LIB_PATH) for s in src):
         from . import build as _build
@@ -37,6 +40,10 @@ def _load():
                       ctypes.c_double, ctypes.c_int64, ctypes.c_int64, _dp,
                       _dp, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp,
                       _dp, ctypes.c_int]
+    lib.sdc_ref_step_n.restype = ctypes.c_int
+    lib.sdc_ref_step_n.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_int64, ctypes.c_int64, _dp, _dp, _dp,
+                                   ctypes.c_double, ctypes.c_double]
     _lib = lib
     return lib
 
@@ -139,3 +146,28 @@ def window_step_n(u_full, lo, hi, r, nsteps, step0=0, gl=0.0, gr=0.0,
     out = step_n(u_full[a:b], r, nsteps, step0=step0, gl=gl_w, gr=gr_w,
                  src_b=sb, src_a=src_a, tau=tau, h=h, extended=extended)
     return out[lo - a:hi - a]
+
+
+def sdc_step_n(u0, r, k, nsteps, step0=0, gl=0.0, gr=0.0):
+    """The sub-domain scheme with sub-domains of ``k`` nodes (``sdc_ref.c``):
+    advance interior values ``u0`` (u_1..u_n, n + 1 a multiple of 2k) by
+    ``nsteps`` levels from global level ``step0``; walls as in ``step_n``
+    (no source).  Returns the new array."""
+    lib = _load()
+    u = np.array(u0, dtype=np.float64, copy=True).ravel()
+    n = u.size
+    gla = gra = None
+    gl0 = gr0 = 0.0
+    if np.ndim(gl) == 0:
+        gl0 = float(gl)
+    else:
+        gla = _f64(gl, nsteps + 1, "gl")
+    if np.ndim(gr) == 0:
+        gr0 = float(gr)
+    else:
+        gra = _f64(gr, nsteps + 1, "gr")
+    rc = lib.sdc_ref_step_n(n, int(k), float(r), int(step0), int(nsteps), _ptr(u),
+                            _ptr(gla), _ptr(gra), gl0, gr0)
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments (n + 1 must be a multiple of 2k)")
+    return u

@@ -14,7 +14,7 @@ def build(verbose: bool = False) -> str:
     cmd = [
         "gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off",
         "-fno-fast-math", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra",
-        os.path.join(HERE, "ge_ref.c"), "-o", LIB + ".tmp",
+        os.path.join(HERE, "ge_ref.c"), os.path.join(HERE, "sdc_ref.c"), "-o", LIB + ".tmp",
     ]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -97,6 +97,17 @@ typedef struct {
                         /* launch; 2 = persistent single-wave workgroups that */
                         /* sweep several tiles each, loading the next tile    */
                         /* during the current one (waves must be 1)           */
+    int32_t k;          /* sub-domain width (Section 2): 0 or 1 = two-point   */
+                        /* groups, the sweep described above; 2, 4, 8 or 16 = */
+                        /* odd and even sub-domains of k nodes, Eq. (3)/(4)   */
+                        /* where they meet and Saul'yev's schemes A and B,    */
+                        /* Eq. (1)/(2), swept through them; n + 1 must be a   */
+                        /* multiple of 2k, GE_FP64 or GE_FP32, no source and  */
+                        /* no flux; levels of even index take the pairs where */
+                        /* sub-domain couples meet, odd ones the pairs at     */
+                        /* their centres.  One couple (2k nodes) per lane,    */
+                        /* 64 per window; tile must be 0 or 2k, waves 0 or 1, */
+                        /* schedule 0 or 1.                                   */
 } ge_desc;
 
 /* Bytes of device workspace a ge_step_n call on this problem needs (the
@@ -107,7 +118,9 @@ typedef struct {
 size_t ge_workspace_bytes(const ge_desc *desc);
 
 /* Validate `desc` and create a plan in *out.  Errors: GE_ERR_INVALID (null
- * pointer, n < 1, r <= 0, unknown precision, tile/depth/waves out of range),
+ * pointer, n < 1, r <= 0, unknown precision, tile/depth/waves out of range,
+ * k < 0, or k >= 2 with n + 1 not a multiple of 2k), GE_ERR_UNSUPPORTED
+ * (k >= 2 other than 2, 4, 8, 16, or with GE_FP32_COMP or a source),
  * GE_ERR_NONFINITE (r, g_left or g_right not finite), GE_ERR_NOMEM. */
 ge_status ge_plan(ge_plan_t *out, const ge_desc *desc);
 
@@ -130,7 +143,8 @@ void ge_destroy(ge_plan_t plan);
  *            at every new level to flux[0] and flux[1].
  * u and workspace must be 16-byte aligned.  nsteps = 0 enqueues nothing.
  * Errors: GE_ERR_INVALID (null plan/u/workspace, negative step0 or nsteps,
- * misalignment, aliasing, source array missing or unexpected), GE_ERR_HIP. */
+ * misalignment, aliasing, source array missing or unexpected),
+ * GE_ERR_UNSUPPORTED (flux with a sub-domain plan), GE_ERR_HIP. */
 ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0,
                     int64_t nsteps, const double *g_left_t,
                     const double *g_right_t, const double *src_a_t,

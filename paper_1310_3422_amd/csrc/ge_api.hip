@@ -130,10 +130,85 @@ struct ge_plan_s {
     int64_t ntiles;
     bool single;   // the whole rod fits one window: no halo, all levels per launch
     bool persistent;  // multi-tile launches by the persistent single-wave kernel
+    int sdc;       // sub-domain width k >= 2 (the sub-domain scheme), or 0
     double g_left, g_right;
     const void *src_b;
     double c1, c2, cs, e1, e2, es, tau, h;
 };
+
+namespace {
+
+// Levels per launch of the sub-domain scheme when the caller leaves it to
+// the library.
+constexpr int kSdcDepth = 12;
+
+// Halo, in sub-domain couples, for D levels: a wrong value at an open window
+// edge moves at most k + 1 nodes per level, two more for the pair stencil.
+int sdc_halo(int depth, int k) { return (depth * (k + 1) + 2 + 2 * k - 1) / (2 * k); }
+
+ge_status plan_sdc(ge_plan_t *out, const ge_desc *d)
+{
+    const int prec = d->precision, k = d->k;
+    if (!ge::sdc_supported(prec == ge::kFP32C ? ge::kFP64 : prec, k))
+        return fail(GE_ERR_UNSUPPORTED, "ge_plan: sub-domains of %d nodes are not built (2, 4, 8, 16)",
+                    k);
+    if (prec == ge::kFP32C)
+        return fail(GE_ERR_UNSUPPORTED, "ge_plan: the sub-domain scheme runs in FP64 or FP32");
+    if (d->src_b)
+        return fail(GE_ERR_UNSUPPORTED, "ge_plan: the sub-domain scheme takes no source");
+    if ((d->n + 1) % (2 * (int64_t)k) != 0)
+        return fail(GE_ERR_INVALID, "ge_plan: n + 1 = %lld is not a multiple of 2k = %d",
+                    (long long)(d->n + 1), 2 * k);
+    if (d->tile != 0 && d->tile != 2 * k)
+        return fail(GE_ERR_INVALID, "ge_plan: the sub-domain scheme holds 2k = %d points per lane",
+                    2 * k);
+    if (d->waves != 0 && d->waves != 1)
+        return fail(GE_ERR_INVALID, "ge_plan: the sub-domain scheme runs single-wave windows");
+    if (d->schedule < 0 || d->schedule > 1)
+        return fail(GE_ERR_INVALID, "ge_plan: the sub-domain scheme has one schedule");
+    const int depth = d->depth == 0 ? kSdcDepth : d->depth;
+    if (depth < 1)
+        return fail(GE_ERR_INVALID, "ge_plan: depth = %d, need depth >= 1", depth);
+    const int64_t nsdc = (d->n + 1) / (2 * k);
+    const int halo = sdc_halo(depth, k);
+    const bool single = nsdc <= 64;
+    if (!single && 64 - 2 * halo < 16)
+        return fail(GE_ERR_INVALID,
+                    "ge_plan: depth %d needs a halo of %d couples, too wide for 64-couple windows",
+                    depth, halo);
+    ge_plan_s *p = new (std::nothrow) ge_plan_s();
+    if (!p)
+        return fail(GE_ERR_NOMEM, "ge_plan: out of host memory");
+    p->n = d->n;
+    p->r = d->r;
+    p->prec = prec;
+    p->sdc = k;
+    p->tile = 2 * k;
+    p->waves = 1;
+    p->depth = depth;
+    p->window = 64 * 2 * (int64_t)k;
+    p->g_left = d->g_left;
+    p->g_right = d->g_right;
+    p->src_b = nullptr;
+    p->single = single;
+    p->persistent = false;
+    p->halo = single ? 0 : halo;          // in couples
+    p->core = single ? nsdc : 64 - 2 * halo;
+    p->ntiles = (nsdc + p->core - 1) / p->core;
+    const double r = d->r;
+    p->h = 1.0 / (double)(p->n + 1);
+    p->tau = r * p->h * p->h;
+    const ge::SchemeCoef sc = ge::scheme_coef(r);
+    p->c1 = sc.c1;
+    p->c2 = sc.c2;
+    p->cs = sc.cs;
+    p->e1 = (1.0 - r) / (1.0 + r);       // the sweep's own-value weight
+    p->e2 = p->es = 0.0;
+    *out = p;
+    return GE_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -182,6 +257,10 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
         return fail(GE_ERR_INVALID, "ge_plan: src_b must be 16-byte aligned");
 
     const int prec = d->precision;
+    if (d->k < 0)
+        return fail(GE_ERR_INVALID, "ge_plan: k = %d, need k >= 0", d->k);
+    if (d->k >= 2)
+        return plan_sdc(out, d);
     int tile = d->tile, waves = d->waves, depth = d->depth;
     const bool src = d->src_b != nullptr;
     if (depth < 0)
@@ -272,7 +351,7 @@ ge_status ge_plan_config(ge_plan_t plan, int32_t *tile, int32_t *depth, int32_t 
     if (tile) *tile = plan->tile;
     if (depth) *depth = plan->depth;
     if (waves) *waves = plan->waves;
-    if (halo) *halo = plan->halo;
+    if (halo) *halo = plan->sdc ? plan->halo * plan->tile : plan->halo;   // points
     return GE_OK;
 }
 
@@ -308,6 +387,8 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
         if (a0 < b1 && b0 < a1)
             return fail(GE_ERR_INVALID, "ge_step_n: u and workspace overlap");
     }
+    if (plan->sdc && flux)
+        return fail(GE_ERR_UNSUPPORTED, "ge_step_n: the sub-domain scheme keeps no wall flux");
     if (nsteps == 0)
         return GE_OK;
 
@@ -325,6 +406,17 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
     a.gl0 = plan->g_left; a.gr0 = plan->g_right;
     a.tau = plan->tau; a.h = plan->h;
     const bool src = plan->src_b != nullptr;
+    if (plan->sdc) {
+        a.nsdc = (plan->n + 1) / plan->tile;
+        a.ca = plan->e1;
+    }
+    // one launch of whichever kernel the plan runs
+    auto launch = [&](const ge::TileArgs &la) {
+        if (plan->sdc) return ge::launch_sdc(plan->prec, plan->sdc, la, st);
+        if (plan->persistent && !plan->single)
+            return ge::launch_tiles_persistent(plan->prec, plan->tile, src, la, st);
+        return ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, la, st);
+    };
 
     if (plan->single) {
         // in place, bounded work per launch
@@ -338,7 +430,7 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
             a.gl_t = g_left_t ? g_left_t + done : nullptr;
             a.gr_t = g_right_t ? g_right_t + done : nullptr;
             a.src_a = src_a_t ? src_a_t + done : nullptr;
-            hipError_t e = ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, a, st);
+            hipError_t e = launch(a);
             if (e != hipSuccess)
                 return hip_fail(e, "ge_step_n: launch");
         }
@@ -362,9 +454,7 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
         a.gl_t = g_left_t ? g_left_t + done : nullptr;
         a.gr_t = g_right_t ? g_right_t + done : nullptr;
         a.src_a = src_a_t ? src_a_t + done : nullptr;
-        hipError_t e = plan->persistent
-                            ? ge::launch_tiles_persistent(plan->prec, plan->tile, src, a, st)
-                            : ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, a, st);
+        hipError_t e = launch(a);
         if (e != hipSuccess)
             return hip_fail(e, "ge_step_n: launch");
         done += lev;

@@ -30,6 +30,10 @@ struct TileArgs {
     double e1, e2, es;       // tau(1+r)/(1+2r), tau r/(1+2r), tau/(1+r)
     double gl0, gr0;         // constant walls (used when gl_t / gr_t are null)
     double tau, h;           // for the wall-flux diagnostic
+    // sub-domain scheme (launch_sdc): core and halo count sub-domain
+    // couples (one per lane), nsdc of them in the rod
+    int64_t nsdc;
+    double ca;               // (1-r)/(1+r)
 };
 
 // Supported (precision, points per lane, waves per workgroup) choices.
@@ -44,6 +48,11 @@ hipError_t launch_tiles(int prec, int k, int nw, bool src, const TileArgs &a,
 bool persistent_supported(int prec, int k);
 hipError_t launch_tiles_persistent(int prec, int k, bool src, const TileArgs &a,
                                    hipStream_t stream);
+
+// Sub-domain scheme with sub-domains of k = K/2 nodes, one sub-domain couple
+// (K nodes) per lane, single-wave windows of 64 couples (ge_sdc.hip).
+bool sdc_supported(int prec, int k);
+hipError_t launch_sdc(int prec, int k, const TileArgs &a, hipStream_t stream);
 
 // Elementwise conversions for the compensated pair.
 hipError_t launch_comp_to_fp64(const float *pair, double *x, int64_t n, hipStream_t s);

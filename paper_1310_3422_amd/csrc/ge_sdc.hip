@@ -1,0 +1,214 @@
+// The scheme with sub-domains of k nodes (Section 2: the complementary
+// scheme with odd and even sub-domains of width k; Eq. (3)/(4) where
+// sub-domains meet, Saul'yev's scheme A, Eq. (1), and scheme B, Eq. (2),
+// swept through the sub-domains).
+//
+// Nodes x_0..x_M (h = 1/M, M = n + 1 = 2ek); node j is array element j-1.
+// A sub-domain couple (SDC) is an odd sub-domain followed by an even one,
+// 2k = K nodes: SDC i holds nodes iK .. iK+K-1.  Lane l of a window holds
+// array elements [lK, lK + K) of its SDC i, i.e. nodes iK+1 .. iK+K: SDC i
+// without its first node, plus the first node of SDC i+1 (element K-1).
+// With that layout every confluence pair lies inside one lane, and each
+// level needs one value from a neighbouring lane before its sweeps and at
+// most one after.  For the last SDC, element K-1 is the right wall node x_M
+// (one past the array); it holds the wall value of the current level.
+//
+// Levels of even global index take the first kind (pairs where two SDCs
+// meet: nodes (iK-1, iK) = elements K-2, K-1 of lane i-1; scheme A through
+// the odd sub-domain from its first node, B through the even one from its
+// last), odd levels the second kind (pairs at each SDC's centre, nodes
+// (iK+k-1, iK+k) = elements k-2, k-1; B through the odd sub-domain down to
+// its first node, which the lane to the left holds; A through the even one).
+// The pairs take Eq. (3)/(4) with denominator 1 + 2r in second-difference
+// form; a sweep step is fma(c, v_prev, fma(ca, w, c w_other)), c = r/(1+r),
+// ca = (1-r)/(1+r).
+//
+// Temporal blocking: a launch advances `nlev` levels of a window of 64 SDCs
+// and writes back its core.  A wrong value at an open window edge spreads at
+// most k + 1 nodes per level (through a sweep), so the halo is
+// ceil((D (k+1) + 2) / K) whole SDCs on each side (measured tight to within
+// one SDC on the CPU against the oracle).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ge_kernels.h"
+#include "ge_level.h"
+
+namespace ge {
+namespace {
+
+using namespace dev;
+
+template <typename T> struct SdcCoef {
+    T c, ca;      // r/(1+r), (1-r)/(1+r): the sweep step
+    T c1, c2;     // (r+r^2)/(1+2r), r^2/(1+2r): the pair
+};
+
+// in vector registers for FP32 (see lane_coef)
+template <typename T>
+__device__ __forceinline__ SdcCoef<T> sdc_lane_coef(SdcCoef<T> k)
+{
+    if constexpr (sizeof(T) == 4)
+        asm("" : "+v"(k.c), "+v"(k.ca), "+v"(k.c1), "+v"(k.c2));
+    return k;
+}
+
+// Eq. (3)/(4) for the pair (u0, u1), outer neighbours um, u2 (old level)
+template <typename T>
+__device__ __forceinline__ void sdc_pair(T um, T u0, T u1, T u2, const SdcCoef<T> &k, T &n0,
+                                         T &n1)
+{
+    const T dm = u0 - um, d0 = u1 - u0, d1 = u2 - u1;
+    const T Da = d0 - dm, Db = d1 - d0;
+    n0 = fmaT(k.c2, Db, fmaT(k.c1, Da, u0));
+    n1 = fmaT(k.c2, Da, fmaT(k.c1, Db, u1));
+}
+
+// One Saul'yev step: (r v + (1-r) w + r wo) / (1+r), with v the new value
+// of the sweep predecessor and wo the old value of the other neighbour
+template <typename T>
+__device__ __forceinline__ T sweep(T v, T w, T wo, const SdcCoef<T> &k)
+{
+    return fmaT(k.c, v, fmaT(k.ca, w, k.c * wo));
+}
+
+// One level of the lane's SDC.  first / last: the lane holds the rod's first
+// / last SDC (walls); gl_old, gl_new: left wall at this and the next level;
+// gr_new: right wall at the next level.  Values entering from lanes outside
+// the window are zero: they only reach the halo.
+template <typename T, int K, int KIND>
+__device__ __forceinline__ void sdc_level(T (&s)[K], const SdcCoef<T> &cf, bool first, bool last,
+                                          T gl_old, T gl_new, T gr_new)
+{
+    constexpr int k = K / 2;
+    static_assert(k >= 2, "sub-domains of two or more nodes");
+    if constexpr (KIND == 1) {
+        // pair at the boundary with the next SDC: elements K-2, K-1
+        const T oR = from_right(T(0), s[0]);
+        T pA, pB;
+        sdc_pair(s[K - 3], s[K - 2], s[K - 1], oR, cf, pA, pB);
+        if (last) {
+            // node M-1 by scheme B against the wall, node M the wall
+            pA = sweep(gr_new, s[K - 2], s[K - 3], cf);
+            pB = gr_new;
+        }
+        // scheme A through the odd sub-domain, from its first node (the
+        // left lane's pair value, or the left wall)
+        T v = from_left(T(0), pB);
+        if (first) v = gl_new;
+        const T o_odd_last = s[k - 2];
+#pragma unroll
+        for (int e = 0; e <= k - 2; ++e) {
+            v = sweep(v, s[e], s[e + 1], cf);
+            s[e] = v;
+        }
+        // scheme B through the even sub-domain, from its last node
+        v = pA;
+#pragma unroll
+        for (int e = K - 3; e >= k - 1; --e) {
+            const T prv = (e - 1 == k - 2) ? o_odd_last : s[e - 1];
+            v = sweep(v, s[e], prv, cf);
+            s[e] = v;
+        }
+        s[K - 2] = pA;
+        s[K - 1] = pB;
+    } else {
+        // node iK (this SDC's first node) lives in the left lane
+        const T fl = from_left(T(0), s[K - 1]);
+        const T oL = first ? gl_old : fl;
+        // pair at the centre: elements k-2, k-1
+        T qA, qB;
+        sdc_pair(k == 2 ? oL : s[k == 2 ? 0 : k - 3], s[k - 2], s[k - 1], s[k], cf, qA, qB);
+        const T o_last = s[K - 1], o_prev = s[K - 2];
+        // scheme B down the odd sub-domain
+        T v = qA;
+#pragma unroll
+        for (int e = k - 3; e >= 0; --e) {
+            const T prv = e >= 1 ? s[e - 1] : oL;
+            v = sweep(v, s[e], prv, cf);
+            s[e] = v;
+        }
+        // scheme A up the even sub-domain
+        v = qB;
+#pragma unroll
+        for (int e = k; e <= K - 2; ++e) {
+            v = sweep(v, s[e], s[e + 1], cf);
+            s[e] = v;
+        }
+        s[k - 2] = qA;
+        s[k - 1] = qB;
+        // element K-1 is the first node of the next SDC, the end of its
+        // scheme-B sweep: it needs that lane's new element 0
+        const T r0 = from_right(T(0), s[0]);
+        const T nk = sweep(r0, o_last, o_prev, cf);
+        s[K - 1] = last ? gr_new : nk;
+    }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(kWave) void sdc_tile_kernel(TileArgs a)
+{
+    // consecutive tiles on one XCD, as in the two-point sweep
+    const int64_t per = gridDim.x / 8;
+    const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= a.ntiles)
+        return;
+    const int lane = threadIdx.x;
+    const int64_t c0 = t * a.core;                              // first core SDC
+    const int64_t w0 = c0 - a.halo < 0 ? 0 : c0 - a.halo;       // first SDC of the window
+    const int64_t i = w0 + lane;                                // this lane's SDC
+    const int64_t g0 = i * K;                                   // its first array element
+    const T *in = static_cast<const T *>(a.in);
+    T *out = static_cast<T *>(a.out);
+    T s[K];
+    load_lane_guarded<T, K>(in + g0, g0, a.n, s);
+    const bool first = (i == 0), last = (i == a.nsdc - 1);
+    auto gl = [&](int lev) { return a.gl_t ? a.gl_t[lev] : a.gl0; };
+    auto gr = [&](int lev) { return a.gr_t ? a.gr_t[lev] : a.gr0; };
+    if (last) s[K - 1] = (T)gr(0);
+    const SdcCoef<T> cf = sdc_lane_coef(SdcCoef<T>{(T)a.cs, (T)a.ca, (T)a.c1, (T)a.c2});
+    for_levels(a.level0, a.nlev, [&](auto par, int lev) {
+        constexpr int p = decltype(par)::value;
+        sdc_level<T, K, p == 0 ? 1 : 2>(s, cf, first, last, (T)gl(lev), (T)gl(lev + 1),
+                                         (T)gr(lev + 1));
+    });
+    const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
+    if (i >= c0 && i < c1)
+        store_lane_upto<T, K>(out + g0, g0, a.n, s);
+}
+
+template <typename T, int K>
+hipError_t launch_one_sdc(const TileArgs &a, hipStream_t stream)
+{
+    const int64_t grid = (a.ntiles + 7) / 8 * 8;
+    hipLaunchKernelGGL((sdc_tile_kernel<T, K>), dim3((unsigned)grid), dim3(kWave), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sdc_t(int k, const TileArgs &a, hipStream_t stream)
+{
+    switch (k) {
+    case 2: return launch_one_sdc<T, 4>(a, stream);
+    case 4: return launch_one_sdc<T, 8>(a, stream);
+    case 8: return launch_one_sdc<T, 16>(a, stream);
+    case 16: return launch_one_sdc<T, 32>(a, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool sdc_supported(int prec, int k)
+{
+    return (prec == kFP64 || prec == kFP32) && (k == 2 || k == 4 || k == 8 || k == 16);
+}
+
+hipError_t launch_sdc(int prec, int k, const TileArgs &a, hipStream_t stream)
+{
+    if (prec == kFP64) return launch_sdc_t<double>(k, a, stream);
+    if (prec == kFP32) return launch_sdc_t<float>(k, a, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ge

@@ -26,7 +26,7 @@ _dbl = ctypes.c_double
 class GeDesc(ctypes.Structure):
     _fields_ = [("n", _i64), ("r", _dbl), ("precision", _i32), ("tile", _i32),
                 ("depth", _i32), ("waves", _i32), ("g_left", _dbl),
-                ("g_right", _dbl), ("src_b", _vp), ("schedule", _i32)]
+                ("g_right", _dbl), ("src_b", _vp), ("schedule", _i32), ("k", _i32)]
 
 
 class GeBatchDesc(ctypes.Structure):
@@ -150,7 +150,7 @@ class Plan:
     """A ge_plan for one rod; ``step_n`` advances a device state tensor."""
 
     def __init__(self, n, r, precision="fp64", g_left=0.0, g_right=0.0, src_b=None,
-                 tile=0, depth=0, waves=0, schedule=0):
+                 tile=0, depth=0, waves=0, schedule=0, k=0):
         self.n, self.r = int(n), float(r)
         self.precision = _prec(precision)
         self._src_b = src_b   # keep the profile alive
@@ -158,7 +158,9 @@ class Plan:
             self._check_tensor(src_b, self.n, "src_b", state_dtype(self.precision))
         self.desc = GeDesc(n=self.n, r=self.r, precision=self.precision, tile=tile,
                            depth=depth, waves=waves, g_left=float(g_left),
-                           g_right=float(g_right), src_b=_ptr(src_b), schedule=int(schedule))
+                           g_right=float(g_right), src_b=_ptr(src_b), schedule=int(schedule),
+                           k=int(k))
+        self.k = int(k)
         h = _vp()
         check(lib().ge_plan(ctypes.byref(h), ctypes.byref(self.desc)))
         self.handle = h
@@ -174,8 +176,11 @@ class Plan:
         t, d, w, h = _i32(), _i32(), _i32(), _i32()
         check(lib().ge_plan_config(self.handle, ctypes.byref(t), ctypes.byref(d),
                                    ctypes.byref(w), ctypes.byref(h)))
-        return {"tile": t.value, "depth": d.value, "waves": w.value, "halo": h.value,
-                "schedule": int(lib().ge_plan_schedule(self.handle))}
+        out = {"tile": t.value, "depth": d.value, "waves": w.value, "halo": h.value,
+               "schedule": int(lib().ge_plan_schedule(self.handle))}
+        if self.k >= 2:
+            out["k"] = self.k
+        return out
 
     @staticmethod
     def _check_tensor(t, numel, name, dtype):

@@ -277,3 +277,33 @@ def test_default_tile_follows_depth_and_source(prec, depth, src, want):
     ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w), ctypes.byref(hal))
     assert (t.value, w.value, d.value, ge.lib().ge_plan_schedule(h)) == want
     ge.lib().ge_destroy(h)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=31, k=-1), ge.GE_ERR_INVALID),
+    (dict(n=35, k=3), ge.GE_ERR_UNSUPPORTED),
+    (dict(n=30, k=2), ge.GE_ERR_INVALID),                 # n + 1 not a multiple of 4
+    (dict(n=31, k=4, precision=2), ge.GE_ERR_UNSUPPORTED),
+    (dict(n=31, k=4, src_b=ctypes.c_void_p(0x1000)), ge.GE_ERR_UNSUPPORTED),
+    (dict(n=31, k=4, tile=16), ge.GE_ERR_INVALID),
+    (dict(n=31, k=4, waves=4), ge.GE_ERR_INVALID),
+    (dict(n=32 * 1000 - 1, k=16, depth=60), ge.GE_ERR_INVALID),   # halo wider than the window allows
+])
+def test_subdomain_plan_rejects(kw, status):
+    st, h = _plan(**kw)
+    assert st == status, ge.last_error()
+    assert not h.value
+
+
+def test_subdomain_plan_config():
+    st, h = _plan(n=32 * 1000 - 1, k=16)
+    assert st == ge.GE_OK
+    t, d, w, hal = (ctypes.c_int32() for _ in range(4))
+    ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w), ctypes.byref(hal))
+    # 12 levels: a halo of ceil((12 * 17 + 2) / 32) = 7 couples of 32 points
+    assert (t.value, d.value, w.value, hal.value) == (32, 12, 1, 224)
+    fake = ctypes.c_void_p(0x1000)
+    flux = ctypes.c_void_p(0x2000)
+    assert ge.lib().ge_step_n(h, fake, ctypes.c_void_p(0x100000), 0, 1, None, None, None, flux,
+                              None) == ge.GE_ERR_UNSUPPORTED
+    ge.lib().ge_destroy(h)

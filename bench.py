@@ -372,6 +372,29 @@ def main():
                                    0, 1)
             extra["fp32_compensated"] = {"updates_per_s": n * LEVELS / wc,
                                          "config": pc.config()}
+        # the paper's own configuration: sub-domains of k = 16 nodes (couples
+        # of 32), FP64, a rod of 2^24 - 1 points (n + 1 a multiple of 32),
+        # same r, u0 and level count as the headline rod
+        ns = N_DEFAULT - 1
+        ps = ge.Plan(ns, R, "fp64", k=16)
+        us = ge.pack_state(u0[:ns], "fp64")
+        wss = ps.new_workspace()
+        with torch.cuda.stream(stream):
+            torch.cuda.synchronize()
+            wsd, gsd = time_runs(torch, stream,
+                                 lambda: ps.step_n(us, 0, LEVELS, workspace=wss, stream=stream), 1, 3)
+        sups = ns * LEVELS * 3 / gsd
+        # a sweep node costs one multiply and two FMAs (5 flops); the pairs
+        # are a small share at k = 16
+        speak = VALU_LANE_OPS * 5 / 3 / 1e12
+        extra["subdomain_k16_fp64"] = {
+            "updates_per_s": sups, "n": ns, "k": 16, "levels": LEVELS, "config": ps.config(),
+            "roofline": {"bound": "alu", "achieved": round(sups * 5 / 1e12, 2),
+                         "peak": round(speak, 1), "unit": "TFLOP/s",
+                         "frac": round(sups * 5 / 1e12 / speak, 4),
+                         "peak_basis": "VALU issue 3.93e13 lane-ops/s x 5 flops / 3 VALU ops "
+                                       "per sweep node"}}
+        del us, wss, ps
         # batch of 4096 independent rods (N log-uniform in [256, 65536],
         # r in [0.25, 4], walls in [-1, 1], seed 3), 2000 levels, FP32, one
         # persistent graph-captured launch

@@ -140,10 +140,10 @@ namespace {
 
 // Levels per launch of the sub-domain scheme when the caller leaves it to
 // the library: measured on MI355X (2^24 points, k = 8 and 16, FP64 and
-// FP32), updates/s rise with the depth up to 24-32 levels, where the
-// widening halo (13 couples a side at k = 16) catches up with the saved
-// HBM traffic.
-constexpr int kSdcDepth = 24;
+// FP32), updates/s rise with the depth up to 16-24 levels, where the
+// widening halo (11 couples a side at k = 16 and 20 levels) catches up with
+// the saved HBM traffic.
+constexpr int kSdcDepth = 20;
 
 // Halo, in sub-domain couples, for D levels: a wrong value at an open window
 // edge moves at most k + 1 nodes per level, two more for the pair stencil.

@@ -21,10 +21,11 @@
 // its first node, which the lane to the left holds; A through the even one).
 // The pairs take Eq. (3)/(4) with denominator 1 + 2r in second-difference
 // form; a sweep step is fma(c, v_prev, fma(ca, w, c w_other)), c = r/(1+r),
-// ca = (1-r)/(1+r).
+// ca = (1-r)/(1+r), taken two nodes at a time (see sweep_run).
 //
 // Temporal blocking: a launch advances `nlev` levels of a window of 64 SDCs
-// and writes back its core.  A wrong value at an open window edge spreads at
+// and writes back its core; the window moves through LDS on the way in and
+// out, so that HBM sees consecutive 16-byte chunks across the lanes.  A wrong value at an open window edge spreads at
 // most k + 1 nodes per level (through a sweep), so the halo is
 // ceil((D (k+1) + 2) / K) whole SDCs on each side (measured tight to within
 // one SDC on the CPU against the oracle).
@@ -42,14 +43,16 @@ using namespace dev;
 template <typename T> struct SdcCoef {
     T c, ca;      // r/(1+r), (1-r)/(1+r): the sweep step
     T c1, c2;     // (r+r^2)/(1+2r), r^2/(1+2r): the pair
+    T cc;         // c * c: two sweep steps at once
 };
 
 // in vector registers for FP32 (see lane_coef)
 template <typename T>
 __device__ __forceinline__ SdcCoef<T> sdc_lane_coef(SdcCoef<T> k)
 {
+    k.cc = k.c * k.c;
     if constexpr (sizeof(T) == 4)
-        asm("" : "+v"(k.c), "+v"(k.ca), "+v"(k.c1), "+v"(k.c2));
+        asm("" : "+v"(k.c), "+v"(k.ca), "+v"(k.c1), "+v"(k.c2), "+v"(k.cc));
     return k;
 }
 
@@ -70,6 +73,37 @@ template <typename T>
 __device__ __forceinline__ T sweep(T v, T w, T wo, const SdcCoef<T> &k)
 {
     return fmaT(k.c, v, fmaT(k.ca, w, k.c * wo));
+}
+
+// A sweep through elements FROM..TO (in either direction) of the lane's
+// registers, starting from the new value v of the node before FROM.  The
+// recurrence v_e = c v_prev + t_e, t_e = ca w_e + c wo_e, is a chain of
+// dependent FMAs; two steps are taken at once, v_{e+1} = c^2 v + (c t_e +
+// t_{e+1}), with v_e off the chain, which halves its length.  other(e) is
+// the old value of e's neighbour on the far side (read before anything is
+// written over it).  Returns the value of the last node.
+template <typename T, int K, int FROM, int TO, typename Other>
+__device__ __forceinline__ T sweep_run(T (&s)[K], T v, const SdcCoef<T> &k, Other other)
+{
+    constexpr int step = FROM <= TO ? 1 : -1;
+    constexpr int len = (TO - FROM) * step + 1;
+#pragma unroll
+    for (int j = 0; j + 1 < len; j += 2) {
+        const int e0 = FROM + j * step, e1 = e0 + step;
+        const T t0 = fmaT(k.ca, s[e0], k.c * other(e0));
+        const T t1 = fmaT(k.ca, s[e1], k.c * other(e1));
+        const T u = fmaT(k.c, t0, t1);
+        const T v0 = fmaT(k.c, v, t0);
+        v = fmaT(k.cc, v, u);
+        s[e0] = v0;
+        s[e1] = v;
+    }
+    if constexpr (len % 2 == 1) {
+        constexpr int e = TO;
+        v = fmaT(k.c, v, fmaT(k.ca, s[e], k.c * other(e)));
+        s[e] = v;
+    }
+    return v;
 }
 
 // One level of the lane's SDC.  first / last: the lane holds the rod's first
@@ -97,19 +131,10 @@ __device__ __forceinline__ void sdc_level(T (&s)[K], const SdcCoef<T> &cf, bool 
         T v = from_left(T(0), pB);
         if (first) v = gl_new;
         const T o_odd_last = s[k - 2];
-#pragma unroll
-        for (int e = 0; e <= k - 2; ++e) {
-            v = sweep(v, s[e], s[e + 1], cf);
-            s[e] = v;
-        }
+        sweep_run<T, K, 0, k - 2>(s, v, cf, [&](int e) { return s[e + 1]; });
         // scheme B through the even sub-domain, from its last node
-        v = pA;
-#pragma unroll
-        for (int e = K - 3; e >= k - 1; --e) {
-            const T prv = (e - 1 == k - 2) ? o_odd_last : s[e - 1];
-            v = sweep(v, s[e], prv, cf);
-            s[e] = v;
-        }
+        sweep_run<T, K, K - 3, k - 1>(s, pA, cf,
+                                      [&](int e) { return e - 1 == k - 2 ? o_odd_last : s[e - 1]; });
         s[K - 2] = pA;
         s[K - 1] = pB;
     } else {
@@ -121,20 +146,10 @@ __device__ __forceinline__ void sdc_level(T (&s)[K], const SdcCoef<T> &cf, bool 
         sdc_pair(k == 2 ? oL : s[k == 2 ? 0 : k - 3], s[k - 2], s[k - 1], s[k], cf, qA, qB);
         const T o_last = s[K - 1], o_prev = s[K - 2];
         // scheme B down the odd sub-domain
-        T v = qA;
-#pragma unroll
-        for (int e = k - 3; e >= 0; --e) {
-            const T prv = e >= 1 ? s[e - 1] : oL;
-            v = sweep(v, s[e], prv, cf);
-            s[e] = v;
-        }
+        if constexpr (k >= 3)
+            sweep_run<T, K, k - 3, 0>(s, qA, cf, [&](int e) { return e >= 1 ? s[e - 1] : oL; });
         // scheme A up the even sub-domain
-        v = qB;
-#pragma unroll
-        for (int e = k; e <= K - 2; ++e) {
-            v = sweep(v, s[e], s[e + 1], cf);
-            s[e] = v;
-        }
+        sweep_run<T, K, k, K - 2>(s, qB, cf, [&](int e) { return s[e + 1]; });
         s[k - 2] = qA;
         s[k - 1] = qB;
         // element K-1 is the first node of the next SDC, the end of its
@@ -142,6 +157,100 @@ __device__ __forceinline__ void sdc_level(T (&s)[K], const SdcCoef<T> &cf, bool 
         const T r0 = from_right(T(0), s[0]);
         const T nk = sweep(r0, o_last, o_prev, cf);
         s[K - 1] = last ? gr_new : nk;
+    }
+}
+
+// A window's 64 K values go between HBM and the lanes through LDS: the
+// global side moves consecutive 16-byte chunks across the lanes (coalesced;
+// a lane's own K values are 16 K bytes apart from its neighbours'), the LDS
+// side hands each lane its row.  Rows are padded by 16 bytes, so the 16
+// lanes of a row read hit distinct banks.
+template <typename T, int K>
+struct Stage {
+    static constexpr int E = 16 / sizeof(T);          // values per chunk
+    static constexpr int P = K + E;                   // padded row
+    static constexpr int CH = kWave * K / E;          // chunks per window
+};
+
+// values base .. base + 64K of `in` (those below n; zero beyond) into the
+// lanes' rows
+template <typename T, int K>
+__device__ __forceinline__ void stage_load(const T *__restrict__ in, int64_t base, int64_t n,
+                                           T *lds, T (&s)[K])
+{
+    using S = Stage<T, K>;
+    using V = typename V16<T>::type;
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < S::CH / kWave; ++j) {
+        const int c = j * kWave + lane;               // chunk of the window
+        const int e0 = c * S::E;                      // its first value
+        const int64_t g = base + e0;
+        V x;
+        if (g + S::E <= n) {
+            x = *reinterpret_cast<const V *>(in + g);
+        } else {
+            T t[S::E];
+#pragma unroll
+            for (int q = 0; q < S::E; ++q) t[q] = (g + q < n) ? in[g + q] : T(0);
+            if constexpr (S::E == 4) x = V{t[0], t[1], t[2], t[3]};
+            else x = V{t[0], t[1]};
+        }
+        *reinterpret_cast<V *>(&lds[(e0 / K) * S::P + e0 % K]) = x;
+    }
+    __syncthreads();
+    const V *row = reinterpret_cast<const V *>(&lds[lane * S::P]);
+#pragma unroll
+    for (int q = 0; q < K / S::E; ++q) {
+        const V x = row[q];
+        if constexpr (S::E == 4) {
+            s[4 * q] = x.x; s[4 * q + 1] = x.y; s[4 * q + 2] = x.z; s[4 * q + 3] = x.w;
+        } else {
+            s[2 * q] = x.x; s[2 * q + 1] = x.y;
+        }
+    }
+    __syncthreads();   // the rows are free again
+}
+
+// the lanes' rows back to `out`, values of window positions [lo, hi) that
+// lie below n (lo, hi multiples of K)
+template <typename T, int K>
+__device__ __forceinline__ void stage_store(T *__restrict__ out, int64_t base, int64_t n, int lo,
+                                            int hi, T *lds, const T (&s)[K])
+{
+    using S = Stage<T, K>;
+    using V = typename V16<T>::type;
+    const int lane = threadIdx.x;
+    V *row = reinterpret_cast<V *>(&lds[lane * S::P]);
+#pragma unroll
+    for (int q = 0; q < K / S::E; ++q) {
+        V x;
+        if constexpr (S::E == 4) x = V{s[4 * q], s[4 * q + 1], s[4 * q + 2], s[4 * q + 3]};
+        else x = V{s[2 * q], s[2 * q + 1]};
+        row[q] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < S::CH / kWave; ++j) {
+        const int c = j * kWave + lane;
+        const int e0 = c * S::E;
+        if (e0 < lo || e0 >= hi)
+            continue;
+        const int64_t g = base + e0;
+        const V x = *reinterpret_cast<const V *>(&lds[(e0 / K) * S::P + e0 % K]);
+        if (g + S::E <= n) {
+            *reinterpret_cast<V *>(out + g) = x;
+        } else {
+            T u[S::E];
+            if constexpr (S::E == 4) {
+                u[0] = x.x; u[1] = x.y; u[2] = x.z; u[3] = x.w;
+            } else {
+                u[0] = x.x; u[1] = x.y;
+            }
+#pragma unroll
+            for (int q = 0; q < S::E; ++q)
+                if (g + q < n) out[g + q] = u[q];
+        }
     }
 }
 
@@ -157,11 +266,11 @@ __global__ __launch_bounds__(kWave) void sdc_tile_kernel(TileArgs a)
     const int64_t c0 = t * a.core;                              // first core SDC
     const int64_t w0 = c0 - a.halo < 0 ? 0 : c0 - a.halo;       // first SDC of the window
     const int64_t i = w0 + lane;                                // this lane's SDC
-    const int64_t g0 = i * K;                                   // its first array element
     const T *in = static_cast<const T *>(a.in);
     T *out = static_cast<T *>(a.out);
+    __shared__ __attribute__((aligned(16))) T lds[kWave * Stage<T, K>::P];
     T s[K];
-    load_lane_guarded<T, K>(in + g0, g0, a.n, s);
+    stage_load<T, K>(in, w0 * K, a.n, lds, s);
     const bool first = (i == 0), last = (i == a.nsdc - 1);
     auto gl = [&](int lev) { return a.gl_t ? a.gl_t[lev] : a.gl0; };
     auto gr = [&](int lev) { return a.gr_t ? a.gr_t[lev] : a.gr0; };
@@ -173,8 +282,7 @@ __global__ __launch_bounds__(kWave) void sdc_tile_kernel(TileArgs a)
                                          (T)gr(lev + 1));
     });
     const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
-    if (i >= c0 && i < c1)
-        store_lane_upto<T, K>(out + g0, g0, a.n, s);
+    stage_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds, s);
 }
 
 template <typename T, int K>

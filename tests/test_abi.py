@@ -300,8 +300,8 @@ def test_subdomain_plan_config():
     assert st == ge.GE_OK
     t, d, w, hal = (ctypes.c_int32() for _ in range(4))
     ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w), ctypes.byref(hal))
-    # 24 levels: a halo of ceil((24 * 17 + 2) / 32) = 13 couples of 32 points
-    assert (t.value, d.value, w.value, hal.value) == (32, 24, 1, 416)
+    # 20 levels: a halo of ceil((20 * 17 + 2) / 32) = 11 couples of 32 points
+    assert (t.value, d.value, w.value, hal.value) == (32, 20, 1, 352)
     fake = ctypes.c_void_p(0x1000)
     flux = ctypes.c_void_p(0x2000)
     assert ge.lib().ge_step_n(h, fake, ctypes.c_void_p(0x100000), 0, 1, None, None, None, flux,

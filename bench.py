@@ -14,7 +14,9 @@ Prints one JSON line.  Beside the headline value it carries
                  bounded number of levels of the same rod;
   extra        : the depth-1 streaming sweep against HBM bandwidth, the
                  compensated FP32 form on the same rod, and a sampled parity
-                 check of the timed result against the oracle.
+                 check of the timed result against the oracle;
+  paper_e2_shape : the paper's timing runs (about 2.6e5 nodes, 20 to 1200
+                 time rows) on the GPU and on the CPU oracle.
 """
 import argparse
 import json
@@ -140,6 +142,68 @@ def cpu_baseline(u0, target_s):
                               "sample": f"first {lv1} levels, 1 thread, {dt1:.1f} s "
                                         "(rate extrapolated to the whole run)"},
             "host_cpu": model}
+
+
+# The paper's timing runs, reshaped for one MI355X: about 8208 sub-domain
+# couples of 32 nodes per time row (k = 16), 20 to 1200 time rows; the GPU
+# against the CPU oracle on one thread and on all host cores.
+E2_N = 8208 * 32 - 1
+E2_ROWS = (20, 100, 400, 1200)
+
+
+def paper_e2_table(torch, stream, ge, inputs):
+    """GPU seconds per run of `rows` levels (median of 5 calls, HIP events on
+    the call's stream) for the sub-domain scheme (k = 16) and the two-point
+    groups, FP32 and FP64, beside the CPU oracle's seconds for the same run:
+    the sub-domain oracle (serial) and the two-point oracle on one thread and
+    on all host cores."""
+    import oracle
+    threads = os.cpu_count() or 1
+    u0 = inputs.sine_rod(E2_N, seed=2)
+    out = {"n": E2_N, "k": 16, "r": R, "rows": list(E2_ROWS), "gpu_s": {}, "cpu_s": {}}
+    for name, k, prec in (("subdomain_k16_fp32", 16, "fp32"), ("subdomain_k16_fp64", 16, "fp64"),
+                          ("groups_fp32", 0, "fp32"), ("groups_fp64", 0, "fp64")):
+        plan = ge.Plan(E2_N, R, prec, k=k)
+        u = ge.pack_state(u0, prec)
+        ws = plan.new_workspace()
+        col = []
+        with torch.cuda.stream(stream):
+            for rows in E2_ROWS:
+                plan.step_n(u, 0, rows, workspace=ws, stream=stream)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(5):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    plan.step_n(u, 0, rows, workspace=ws, stream=stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1) / 1e3)
+                col.append(float(np.median(ts)))
+        out["gpu_s"][name] = col
+        del plan, u, ws
+    for name, fn in (("subdomain_k16_1thread", lambda rows: oracle.sdc_step_n(u0, R, 16, rows)),
+                     ("groups_1thread", lambda rows: oracle.step_n(u0, R, rows, nthreads=1)),
+                     ("groups_all_cores", lambda rows: oracle.step_n(u0, R, rows, nthreads=threads))):
+        col = []
+        for rows in E2_ROWS:
+            t = time.perf_counter()
+            fn(rows)
+            col.append(time.perf_counter() - t)
+        out["cpu_s"][name] = col
+    last = -1
+    out["speedup_at_1200_rows"] = {
+        "subdomain_fp32_over_1thread": round(out["cpu_s"]["subdomain_k16_1thread"][last]
+                                             / out["gpu_s"]["subdomain_k16_fp32"][last], 1),
+        "groups_fp64_over_1thread": round(out["cpu_s"]["groups_1thread"][last]
+                                          / out["gpu_s"]["groups_fp64"][last], 1),
+        "groups_fp64_over_all_cores": round(out["cpu_s"]["groups_all_cores"][last]
+                                            / out["gpu_s"]["groups_fp64"][last], 1)}
+    out["cores"] = threads
+    out["note"] = ("CPU: FP64 C oracle, untuned; the sub-domain oracle is serial, so the "
+                   "all-core figure is the two-point-group scheme's")
+    return out
 
 
 def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
@@ -432,6 +496,9 @@ def main():
             "single_thread": round(value / cb["single_thread"]["value"], 1),
             "paper_context": "GT 335M vs i7-720QM: about 5x over 1 thread, about 2x over "
                              "8 threads (sub-domain scheme, relative figures only)"}
+        if not args.no_extra:
+            print("[bench] paper-shaped timing table ...", file=sys.stderr, flush=True)
+            out["paper_e2_shape"] = paper_e2_table(torch, stream, ge, inputs)
 
     print(json.dumps(out), flush=True)
     return 0

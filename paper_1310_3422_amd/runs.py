@@ -7,8 +7,16 @@
         the sub-domain scheme on a rod of 2^24 - 1 points (16-mode sine u0,
         seed 2, r = 2)
 
-Each prints one JSON line with the elapsed time of the run (HIP events on
-its stream, after one untimed warm-up run).
+    python -m paper_1310_3422_amd.runs occupancy [--precision fp32] [--levels 1200]
+        the paper's node-rate experiments at MI355X scale: at the paper's row
+        of 8208 x 32 - 1 points, updates/s against the number of workgroups
+        (tile and waves of the two-point-group sweep, depth 8, one workgroup
+        per tile); then updates/s against the rod length (32 * 2^j - 1
+        points, j = 8..19) for the sub-domain scheme (k = 16) and the
+        two-point groups at the library's choices
+
+Each prints JSON lines with the elapsed time of the run (HIP events on its
+stream, after one untimed warm-up run).
 """
 import argparse
 import json
@@ -58,6 +66,43 @@ def subdomain(k, precision, levels):
             "s": s, "updates_per_s": n * levels / s, "config": plan.config()}
 
 
+def occupancy(precision, levels):
+    import torch
+    from . import ge, inputs
+    stream = torch.cuda.Stream()
+    n = 8208 * 32 - 1
+    u0 = inputs.sine_rod(n, 2)
+    for waves in (1, 4):
+        for tile in ((2, 4, 8, 16, 32) if precision == "fp64" else (4, 8, 16, 32)):
+            plan = ge.Plan(n, 2.0, precision, tile=tile, waves=waves, depth=8, schedule=1)
+            cfg = plan.config()
+            window = 64 * waves * tile
+            wgs = 1 if n <= window else -(-n // (window - 2 * cfg["halo"]))
+            u = ge.pack_state(u0, precision)
+            ws = plan.new_workspace()
+            with torch.cuda.stream(stream):
+                s = _timed(torch, stream,
+                           lambda: plan.step_n(u, 0, levels, workspace=ws, stream=stream))
+            yield {"sweep": "workgroups", "precision": precision, "n": n, "levels": levels,
+                   "tile": tile, "waves": waves, "workgroups": wgs, "s": s,
+                   "updates_per_s": n * levels / s}
+            del plan, u, ws
+    for j in range(8, 20):
+        n = 32 * (1 << j) - 1
+        u0 = inputs.sine_rod(n, 2)
+        for k in (16, 0):
+            plan = ge.Plan(n, 2.0, precision, k=k)
+            u = ge.pack_state(u0, precision)
+            ws = plan.new_workspace()
+            with torch.cuda.stream(stream):
+                s = _timed(torch, stream,
+                           lambda: plan.step_n(u, 0, levels, workspace=ws, stream=stream))
+            yield {"sweep": "length", "precision": precision, "n": n, "levels": levels,
+                   "scheme": "subdomain_k16" if k else "groups", "config": plan.config(),
+                   "s": s, "updates_per_s": n * levels / s}
+            del plan, u, ws
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -68,11 +113,18 @@ def main(argv=None):
     s.add_argument("--k", type=int, default=16)
     s.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     s.add_argument("--levels", type=int, default=960)
+    o = sub.add_parser("occupancy")
+    o.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    o.add_argument("--levels", type=int, default=1200)
     args = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         print("runs needs a HIP device", file=sys.stderr)
         return 2
+    if args.cmd == "occupancy":
+        for line in occupancy(args.precision, args.levels):
+            print(json.dumps(line), flush=True)
+        return 0
     if args.cmd == "batch":
         out = batch(args.precision, args.levels)
     else:

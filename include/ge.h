@@ -106,8 +106,13 @@ typedef struct {
                         /* no flux; levels of even index take the pairs where */
                         /* sub-domain couples meet, odd ones the pairs at     */
                         /* their centres.  One couple (2k nodes) per lane,    */
-                        /* 64 per window; tile must be 0 or 2k, waves 0 or 1, */
-                        /* schedule 0 or 1.                                   */
+                        /* 64 per window; tile must be 0 or 2k, waves 0 or 1. */
+                        /* Schedule 2 here: resident single-wave workgroups   */
+                        /* that copy the next window from HBM into LDS while  */
+                        /* the current one advances (used from 3 windows on); */
+                        /* the library's choice takes it for GE_FP64 with     */
+                        /* k = 16 from 64 windows on, at 24 levels per launch */
+                        /* (20 otherwise).                                    */
 } ge_desc;
 
 /* Bytes of device workspace a ge_step_n call on this problem needs (the

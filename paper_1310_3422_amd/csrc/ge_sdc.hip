@@ -285,6 +285,255 @@ __global__ __launch_bounds__(kWave) void sdc_tile_kernel(TileArgs a)
     stage_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds, s);
 }
 
+// Persistent form.  Single-wave workgroups stay resident and take the tiles
+// round by round; while a tile advances through its levels, the next tile's
+// window is copied from HBM straight into the wave's LDS buffer
+// (global_load_lds: no registers held), so the HBM traffic of a launch
+// hides behind its arithmetic instead of alternating with it.  When the
+// levels are done the registers and the buffer swap contents chunk by chunk:
+// the registers take the next window, the buffer the results, which then go
+// out in coalesced chunks before the following copy is issued.
+//
+// The buffer holds the window's 64 rows of K values as 16-byte chunks; the
+// chunks of row l sit in the row's slots permuted by XOR with l mod Q (Q
+// chunks per row), so that lanes reading their own rows spread over the
+// banks, while each copy instruction still fills 64 consecutive slots from
+// one contiguous kilobyte of HBM.
+template <typename T, int K>
+struct Swz {
+    static constexpr int E = 16 / sizeof(T);          // values per chunk
+    static constexpr int Q = K / E;                   // chunks per row
+    static_assert(Q >= 1 && (Q & (Q - 1)) == 0, "rows of a power-of-two number of chunks");
+    // slot of chunk q of row l
+    static __device__ __forceinline__ int slot(int l, int q) { return l * Q + (q ^ (l % Q)); }
+    // window chunk held by slot s
+    static __device__ __forceinline__ int chunk(int s)
+    {
+        const int l = s / Q;
+        return l * Q + ((s % Q) ^ (l % Q));
+    }
+};
+
+using lds_void = __attribute__((address_space(3))) void;
+
+// Issue the copy of window values base .. base + 64K of `in` into the
+// buffer.  A chunk that reaches past the rod is replaced by chunk 0 (any
+// valid address; tail_fix overwrites those values).
+template <typename T, int K>
+__device__ __forceinline__ void dma_window(const T *__restrict__ in, int64_t base, int64_t n,
+                                           T *lds)
+{
+    using S = Swz<T, K>;
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < S::Q; ++j) {
+        const int64_t g = base + (int64_t)S::chunk(j * kWave + lane) * S::E;
+        const T *src = g + S::E <= n ? in + g : in;
+        __builtin_amdgcn_global_load_lds(src, (lds_void *)(lds + j * kWave * S::E), 16, 0, 0);
+    }
+}
+
+// the copies into LDS count as vector-memory operations; the compiler does
+// not order LDS reads after them, so the wave waits explicitly
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// LDS reads finished before a copy may overwrite what they read
+__device__ __forceinline__ void wait_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <typename T, int K>
+__device__ __forceinline__ void unpack(const typename V16<T>::type &x, T (&s)[K], int q)
+{
+    if constexpr (V16<T>::E == 4) {
+        s[4 * q] = x.x; s[4 * q + 1] = x.y; s[4 * q + 2] = x.z; s[4 * q + 3] = x.w;
+    } else {
+        s[2 * q] = x.x; s[2 * q + 1] = x.y;
+    }
+}
+
+template <typename T, int K>
+__device__ __forceinline__ typename V16<T>::type pack(const T (&s)[K], int q)
+{
+    using V = typename V16<T>::type;
+    if constexpr (V16<T>::E == 4) return V{s[4 * q], s[4 * q + 1], s[4 * q + 2], s[4 * q + 3]};
+    else return V{s[2 * q], s[2 * q + 1]};
+}
+
+// the lane's row out of the buffer
+template <typename T, int K>
+__device__ __forceinline__ void rows_read(const T *lds, T (&s)[K])
+{
+    using S = Swz<T, K>;
+    using V = typename V16<T>::type;
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < S::Q; ++q)
+        unpack<T, K>(*reinterpret_cast<const V *>(&lds[S::slot(lane, q) * S::E]), s, q);
+}
+
+// the lane's row into the buffer
+template <typename T, int K>
+__device__ __forceinline__ void rows_write(T *lds, const T (&s)[K])
+{
+    using S = Swz<T, K>;
+    using V = typename V16<T>::type;
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < S::Q; ++q)
+        *reinterpret_cast<V *>(&lds[S::slot(lane, q) * S::E]) = pack<T, K>(s, q);
+}
+
+// registers and buffer exchange contents, one chunk at a time (each slot is
+// read before the lane writes it)
+template <typename T, int K>
+__device__ __forceinline__ void rows_swap(T *lds, T (&s)[K])
+{
+    using S = Swz<T, K>;
+    using V = typename V16<T>::type;
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < S::Q; ++q) {
+        V *p = reinterpret_cast<V *>(&lds[S::slot(lane, q) * S::E]);
+        const V x = *p;
+        *p = pack<T, K>(s, q);
+        unpack<T, K>(x, s, q);
+    }
+}
+
+// values of window positions [lo, hi) below n, from the buffer to `out`
+template <typename T, int K>
+__device__ __forceinline__ void chunks_store(T *__restrict__ out, int64_t base, int64_t n, int lo,
+                                             int hi, const T *lds)
+{
+    using S = Swz<T, K>;
+    using V = typename V16<T>::type;
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < S::Q; ++j) {
+        const int sl = j * kWave + lane;
+        const int e0 = S::chunk(sl) * S::E;
+        if (e0 < lo || e0 >= hi)
+            continue;
+        const int64_t g = base + e0;
+        const V x = *reinterpret_cast<const V *>(&lds[sl * S::E]);
+        if (g + S::E <= n) {
+            *reinterpret_cast<V *>(out + g) = x;
+        } else {
+            T u[K];
+            unpack<T, K>(x, u, 0);
+#pragma unroll
+            for (int q = 0; q < S::E; ++q)
+                if (g + q < n) out[g + q] = u[q];
+        }
+    }
+}
+
+// A window that reaches past the rod, after its copy has landed: each lane
+// rewrites its own row in the buffer from plain loads, zero past the rod
+// (the copy read chunk 0 there).  Wave-uniform branch; the loads are waited
+// for inside it, so no load is pending in registers when the branch ends.
+template <typename T, int K>
+__device__ __forceinline__ void tail_fix(const T *__restrict__ in, int64_t base, int64_t n,
+                                         T *lds)
+{
+    if (base + (int64_t)kWave * K <= n)
+        return;
+    const int64_t b = base + (int64_t)threadIdx.x * K;
+    T v[K];
+#pragma unroll
+    for (int e = 0; e < K; ++e)
+        v[e] = b + e < n ? in[b + e] : T(0);
+    rows_write<T, K>(lds, v);
+}
+
+// levels per launch of the persistent form (the wall values of a launch
+// sit in LDS)
+constexpr int kSdcMaxLevels = 64;
+
+template <typename T, int K>
+__global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int nwg)
+{
+    __shared__ __attribute__((aligned(16))) T lds[kWave * K];
+    __shared__ double walls[2][kSdcMaxLevels + 1];
+    const int per = nwg / 8;
+    int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-aware
+    if (t >= a.ntiles)
+        return;
+    const int lane = threadIdx.x;
+    const T *in = static_cast<const T *>(a.in);
+    T *out = static_cast<T *>(a.out);
+    auto wstart = [&](int64_t tt) {
+        const int64_t c0 = tt * a.core;
+        return c0 - a.halo < 0 ? (int64_t)0 : c0 - a.halo;
+    };
+    // The wall values of the launch's levels, read once: inside the loop
+    // every wait on vector memory would also wait for the pending copy.
+    for (int j = lane; j <= a.nlev; j += kWave) {
+        walls[0][j] = a.gl_t ? a.gl_t[j] : a.gl0;
+        walls[1][j] = a.gr_t ? a.gr_t[j] : a.gr0;
+    }
+    auto gl = [&](int lev) { return walls[0][lev]; };
+    auto gr = [&](int lev) { return walls[1][lev]; };
+    T s[K];
+    dma_window<T, K>(in, wstart(t) * K, a.n, lds);
+    wait_vmem();
+    tail_fix<T, K>(in, wstart(t) * K, a.n, lds);
+    rows_read<T, K>(lds, s);
+    const SdcCoef<T> cf = sdc_lane_coef(SdcCoef<T>{(T)a.cs, (T)a.ca, (T)a.c1, (T)a.c2});
+    for (;;) {
+        const int64_t w0 = wstart(t);
+        const int64_t tn = t + nwg;
+        const bool more = tn < a.ntiles;
+        wait_lds();
+        if (more)
+            dma_window<T, K>(in, wstart(tn) * K, a.n, lds);
+        const int64_t i = w0 + lane;
+        const bool first = (i == 0), last = (i == a.nsdc - 1);
+        if (last) s[K - 1] = (T)gr(0);
+        for_levels(a.level0, a.nlev, [&](auto par, int lev) {
+            constexpr int p = decltype(par)::value;
+            sdc_level<T, K, p == 0 ? 1 : 2>(s, cf, first, last, (T)gl(lev), (T)gl(lev + 1),
+                                             (T)gr(lev + 1));
+        });
+        if (more) {
+            wait_vmem();
+            tail_fix<T, K>(in, wstart(tn) * K, a.n, lds);
+            rows_swap<T, K>(lds, s);
+        } else {
+            rows_write<T, K>(lds, s);
+        }
+        const int64_t c0 = t * a.core;
+        const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
+        chunks_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds);
+        if (!more)
+            break;
+        t = tn;
+    }
+}
+
+template <typename T, int K>
+hipError_t launch_persistent_sdc(const TileArgs &a, hipStream_t stream)
+{
+    static int per_cu = 0, ncu = 0;
+    if (per_cu == 0) {
+        int dev = 0, nb = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sdc_persistent_kernel<T, K>, kWave,
+                                                         0) != hipSuccess ||
+            nb < 1 || ncu < 1)
+            return hipErrorInvalidValue;
+        per_cu = nb;
+    }
+    // as many workgroups as stay resident, trimmed so that every one gets
+    // the same number of tiles (to one), in multiples of 8
+    const int64_t cap = (int64_t)per_cu * ncu;
+    const int64_t rounds = (a.ntiles + cap - 1) / cap;
+    int64_t nwg = (a.ntiles + rounds - 1) / rounds;
+    nwg = (nwg + 7) / 8 * 8;
+    hipLaunchKernelGGL((sdc_persistent_kernel<T, K>), dim3((unsigned)nwg), dim3(kWave), 0, stream,
+                       a, (int)nwg);
+    return hipGetLastError();
+}
+
 template <typename T, int K>
 hipError_t launch_one_sdc(const TileArgs &a, hipStream_t stream)
 {
@@ -294,13 +543,13 @@ hipError_t launch_one_sdc(const TileArgs &a, hipStream_t stream)
 }
 
 template <typename T>
-hipError_t launch_sdc_t(int k, const TileArgs &a, hipStream_t stream)
+hipError_t launch_sdc_t(int k, bool persistent, const TileArgs &a, hipStream_t stream)
 {
     switch (k) {
-    case 2: return launch_one_sdc<T, 4>(a, stream);
-    case 4: return launch_one_sdc<T, 8>(a, stream);
-    case 8: return launch_one_sdc<T, 16>(a, stream);
-    case 16: return launch_one_sdc<T, 32>(a, stream);
+    case 2: return persistent ? launch_persistent_sdc<T, 4>(a, stream) : launch_one_sdc<T, 4>(a, stream);
+    case 4: return persistent ? launch_persistent_sdc<T, 8>(a, stream) : launch_one_sdc<T, 8>(a, stream);
+    case 8: return persistent ? launch_persistent_sdc<T, 16>(a, stream) : launch_one_sdc<T, 16>(a, stream);
+    case 16: return persistent ? launch_persistent_sdc<T, 32>(a, stream) : launch_one_sdc<T, 32>(a, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -314,8 +563,17 @@ bool sdc_supported(int prec, int k)
 
 hipError_t launch_sdc(int prec, int k, const TileArgs &a, hipStream_t stream)
 {
-    if (prec == kFP64) return launch_sdc_t<double>(k, a, stream);
-    if (prec == kFP32) return launch_sdc_t<float>(k, a, stream);
+    if (prec == kFP64) return launch_sdc_t<double>(k, false, a, stream);
+    if (prec == kFP32) return launch_sdc_t<float>(k, false, a, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sdc_persistent(int prec, int k, const TileArgs &a, hipStream_t stream)
+{
+    if (a.ntiles < 3 || a.in == a.out || a.nlev > kSdcMaxLevels)
+        return hipErrorInvalidValue;
+    if (prec == kFP64) return launch_sdc_t<double>(k, true, a, stream);
+    if (prec == kFP32) return launch_sdc_t<float>(k, true, a, stream);
     return hipErrorInvalidValue;
 }
 

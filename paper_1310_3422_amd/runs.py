@@ -52,11 +52,11 @@ def batch(precision, levels):
             "rod_k": None}
 
 
-def subdomain(k, precision, levels):
+def subdomain(k, precision, levels, schedule=0, depth=0):
     import torch
     from . import ge, inputs
     n = (1 << 24) - 1
-    plan = ge.Plan(n, 2.0, precision, k=k)
+    plan = ge.Plan(n, 2.0, precision, k=k, schedule=schedule, depth=depth)
     u = ge.pack_state(inputs.sine_rod(n, 2), precision)
     ws = plan.new_workspace()
     stream = torch.cuda.Stream()
@@ -113,6 +113,8 @@ def main(argv=None):
     s.add_argument("--k", type=int, default=16)
     s.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     s.add_argument("--levels", type=int, default=960)
+    s.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2])
+    s.add_argument("--depth", type=int, default=0)
     o = sub.add_parser("occupancy")
     o.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
     o.add_argument("--levels", type=int, default=1200)
@@ -128,7 +130,7 @@ def main(argv=None):
     if args.cmd == "batch":
         out = batch(args.precision, args.levels)
     else:
-        out = subdomain(args.k, args.precision, args.levels)
+        out = subdomain(args.k, args.precision, args.levels, args.schedule, args.depth)
     print(json.dumps(out), flush=True)
     return 0
 

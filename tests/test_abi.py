@@ -288,6 +288,7 @@ def test_default_tile_follows_depth_and_source(prec, depth, src, want):
     (dict(n=31, k=4, tile=16), ge.GE_ERR_INVALID),
     (dict(n=31, k=4, waves=4), ge.GE_ERR_INVALID),
     (dict(n=32 * 1000 - 1, k=16, depth=60), ge.GE_ERR_INVALID),   # halo wider than the window allows
+    (dict(n=31, k=4, schedule=3), ge.GE_ERR_INVALID),
 ])
 def test_subdomain_plan_rejects(kw, status):
     st, h = _plan(**kw)
@@ -300,10 +301,40 @@ def test_subdomain_plan_config():
     assert st == ge.GE_OK
     t, d, w, hal = (ctypes.c_int32() for _ in range(4))
     ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w), ctypes.byref(hal))
-    # 20 levels: a halo of ceil((20 * 17 + 2) / 32) = 11 couples of 32 points
-    assert (t.value, d.value, w.value, hal.value) == (32, 20, 1, 352)
+    # 24 levels (FP64, k = 16): a halo of ceil((24 * 17 + 2) / 32) = 13
+    # couples of 32 points; 27 windows, one workgroup per tile
+    assert (t.value, d.value, w.value, hal.value) == (32, 24, 1, 416)
     fake = ctypes.c_void_p(0x1000)
     flux = ctypes.c_void_p(0x2000)
     assert ge.lib().ge_step_n(h, fake, ctypes.c_void_p(0x100000), 0, 1, None, None, None, flux,
                               None) == ge.GE_ERR_UNSUPPORTED
+    assert ge.lib().ge_plan_schedule(h) == 1
+    ge.lib().ge_destroy(h)
+
+
+@pytest.mark.parametrize("n,schedule,want", [
+    (32 * 1000 - 1, 2, 2),      # 24 tiles of 42 couples: persistent as asked
+    (32 * 100 - 1, 2, 2),       # 3 tiles
+    (32 * 80 - 1, 2, 1),        # 2 tiles: one workgroup per tile
+    (32 * 64 - 1, 2, 1),        # one window, advanced in place
+    (32 * 1000 - 1, 1, 1),
+])
+def test_subdomain_schedule(n, schedule, want):
+    st, h = _plan(n=n, k=16, schedule=schedule)
+    assert st == ge.GE_OK
+    assert ge.lib().ge_plan_schedule(h) == want
+    ge.lib().ge_destroy(h)
+
+
+@pytest.mark.parametrize("prec,k,want", [
+    (0, 16, (24, 2)),          # FP64, couples of 32: persistent, 24 levels
+    (1, 16, (20, 1)),          # FP32
+    (0, 8, (20, 1)),
+])
+def test_subdomain_library_choice(prec, k, want):
+    st, h = _plan(n=(1 << 24) - 1, k=k, precision=prec)
+    assert st == ge.GE_OK
+    t, d, w, hal = (ctypes.c_int32() for _ in range(4))
+    ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w), ctypes.byref(hal))
+    assert (d.value, ge.lib().ge_plan_schedule(h)) == want
     ge.lib().ge_destroy(h)

@@ -28,11 +28,11 @@ def rel_l2(x, y):
     return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
 
 
-def run(u0, r, k, nsteps, precision="fp64", step0=0, gl=0.0, gr=0.0, depth=0):
+def run(u0, r, k, nsteps, precision="fp64", step0=0, gl=0.0, gr=0.0, depth=0, schedule=0):
     n = len(u0)
     scalar_l, scalar_r = np.ndim(gl) == 0, np.ndim(gr) == 0
     plan = ge.Plan(n, r, precision, g_left=gl if scalar_l else 0.0,
-                   g_right=gr if scalar_r else 0.0, depth=depth, k=k)
+                   g_right=gr if scalar_r else 0.0, depth=depth, k=k, schedule=schedule)
     u = ge.pack_state(u0, precision)
     d = lambda a: torch.from_numpy(np.asarray(a, dtype=np.float64)).cuda()
     plan.step_n(u, step0, nsteps, g_left_t=None if scalar_l else d(gl),
@@ -107,3 +107,46 @@ def test_large_rod_fp64():
     got, _ = run(u0, 2.0, k, 120)
     want = oracle.sdc_step_n(u0, 2.0, k, 120)
     assert rel_l2(got, want) < 1e-12
+
+
+# The persistent schedule (resident waves, the next window copied into LDS
+# during the levels) runs the same operations on the same windows as one
+# workgroup per tile: same bits.  Rods of 2^22 - 1 points give thousands of
+# tiles, so every wave takes several in turn; 45 levels at depth 20 make
+# launches of 20, 20 and 5 levels, the third starting on an odd level.
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("k", [2, 4, 8, 16])
+def test_persistent_schedule_gives_the_same_bits(k, precision):
+    n = (1 << 22) - 1
+    u0 = rough(n, 40 + k)
+    ref, c1 = run(u0, 1.9, k, 45, precision=precision, gl=0.2, gr=-0.6, schedule=1)
+    got, c2 = run(u0, 1.9, k, 45, precision=precision, gl=0.2, gr=-0.6, schedule=2)
+    assert (c1["schedule"], c2["schedule"]) == (1, 2)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("k", [2, 16])
+@pytest.mark.parametrize("couples", [3 * 42 - 5, 2 * 42 + 1, 42 * 9 + 40, 5000])
+@pytest.mark.parametrize("step0", [0, 1])
+def test_persistent_schedule_matches_the_oracle(k, couples, step0):
+    """Ragged last tiles whose window reaches past the rod (the tail loads),
+    down to three tiles, against the oracle."""
+    n = 2 * k * couples - 1
+    u0 = rough(n, couples + k)
+    got, cfg = run(u0, 2.3, k, 33, step0=step0, gl=0.4, gr=-0.25, schedule=2)
+    want = oracle.sdc_step_n(u0, 2.3, k, 33, step0=step0, gl=0.4, gr=-0.25)
+    assert rel_l2(got, want) < 1e-12, cfg
+
+
+def test_persistent_schedule_time_dependent_walls():
+    k, n, s = 16, 32 * 3000 - 1, 70
+    rng = np.random.default_rng(9)
+    u0 = rough(n, 9)
+    gl = np.cos(np.linspace(0, 2, s + 1))
+    gr = rng.uniform(-1, 1, s + 1)
+    want = oracle.sdc_step_n(u0, 3.0, k, s, step0=3, gl=gl, gr=gr)
+    got, cfg = run(u0, 3.0, k, s, step0=3, gl=gl, gr=gr, schedule=2)
+    assert cfg["schedule"] == 2
+    assert rel_l2(got, want) < 1e-12
+    ref, _ = run(u0, 3.0, k, s, step0=3, gl=gl, gr=gr, schedule=1)
+    np.testing.assert_array_equal(got, ref)

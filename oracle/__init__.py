@@ -9,6 +9,9 @@ only tests/, the smoke check and the benchmark's CPU-baseline leg use it.
 * ``sdc_step_n``: the same scheme with sub-domains of k nodes (Section 2's
   complementary scheme: Eq. (3)/(4) where sub-domains meet, Saul'yev
   sweeps Eq. (1)/(2) inside them), FP64 (``sdc_ref.c``).
+* ``step2d_n``: the two-dimensional extension on the unit square, the
+  scheme applied along every grid line, x then y, in every level (a
+  composition of ``step_n`` calls).
 * ``conv_ref``: the FP64 forward/backward of the 1D convolutional propagator.
 """
 import ctypes
@@ -170,4 +173,30 @@ def sdc_step_n(u0, r, k, nsteps, step0=0, gl=0.0, gr=0.0):
                             _ptr(gla), _ptr(gra), gl0, gr0)
     if rc != 0:
         raise ValueError("oracle rejected its arguments (n + 1 must be a multiple of 2k)")
+    return u
+
+
+def step2d_n(u0, rx, ry, nsteps, step0=0, walls=(0.0, 0.0, 0.0, 0.0)):
+    """u_t = u_xx + u_yy on the unit square (Section 2's scheme extended to
+    two dimensions, which the paper claims without formulas).  Reading: in
+    every level m the one-dimensional level m is applied along every row
+    (r = rx = tau/hx^2, walls west/east) and then along every column
+    (r = ry = tau/hy^2, walls south/north) -- first-order operator
+    splitting, each line paired by the level's global index as in
+    ``step_n``.
+
+    u0: array (ny, nx); row j holds y_{j+1}, column i holds x_{i+1}, with
+    hx = 1/(nx+1), hy = 1/(ny+1).  walls: constant (west, east, south,
+    north) values.  Returns the new array (u0 is not modified)."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    if u.ndim != 2 or u.shape[0] < 1 or u.shape[1] < 1:
+        raise ValueError("u0 must be a non-empty 2-D array (ny, nx)")
+    ny, nx = u.shape
+    gw, ge_, gs, gn = (float(w) for w in walls)
+    for s in range(nsteps):
+        m = step0 + s
+        for j in range(ny):
+            u[j, :] = step_n(u[j, :], rx, 1, step0=m, gl=gw, gr=ge_)
+        for i in range(nx):
+            u[:, i] = step_n(u[:, i], ry, 1, step0=m, gl=gs, gr=gn)
     return u

@@ -206,6 +206,26 @@ def paper_e2_table(torch, stream, ge, inputs):
     return out
 
 
+def grid2d_extra(torch, stream, ge, inputs, nx=4096, ny=4096, levels=200):
+    """The 2D extension on an nx x ny grid (u0 = sine rod profiles in x times
+    a sine in y, seed 2), one launch per level: updates/s and the kernel
+    against HBM bandwidth (one read and one write of the grid per level)."""
+    fx = inputs.sine_rod(nx, seed=2)
+    y = np.arange(1, ny + 1) / (ny + 1)
+    u = torch.from_numpy(np.outer(np.sin(np.pi * y), fx)).cuda()
+    ws = torch.empty_like(u)
+    with torch.cuda.stream(stream):
+        torch.cuda.synchronize()
+        _, g = time_runs(torch, stream, lambda: ge.step2d_n(u, nx, ny, 2.0, 2.0, 0, levels,
+                                                            workspace=ws, stream=stream), 1, 3)
+    per_level = g / (3 * levels)
+    gbs = 16 * nx * ny / per_level / 1e9
+    return {"updates_per_s": nx * ny * levels * 3 / g, "nx": nx, "ny": ny, "levels": levels,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "basis": "16 B per point and level (FP64 read + write)"}}
+
+
 def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096):
     """The learned 64-level propagator against the plain GE sweep on a batch
     of rods: its training (data from the FP64 batch sweep), its distance from
@@ -480,6 +500,9 @@ def main():
             "ms_per_run": gb / 3 * 1e3, "tasks": info["ntasks"], "workgroups": info["grid"],
             "rods": rb.nrods, "points": int(rb.n.sum()), "levels": 2000}
         del ub, wsb, bt
+        # two-dimensional extension: 4096 x 4096 grid, FP64, rx = ry = 2,
+        # 200 levels (one launch per level, each reading and writing the grid)
+        extra["grid2d_4096_fp64"] = grid2d_extra(torch, stream, ge, inputs)
         if args.surrogate_steps > 0:
             print("[bench] surrogate ...", file=sys.stderr, flush=True)
             extra["surrogate"] = surrogate_extra(torch, stream, args.surrogate_steps)

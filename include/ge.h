@@ -172,6 +172,42 @@ ge_status ge_comp_to_fp64(const float *pair, double *x, int64_t n, void *stream)
 ge_status ge_comp_from_fp64(const double *x, float *pair, int64_t n, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Two-dimensional extension: u_t = u_xx + u_yy on the unit square with
+ * constant Dirichlet walls.  The paper states that the method extends to two
+ * dimensions but gives no formulas; the reading built here applies, in every
+ * level m, the one-dimensional level m of Section 2 (two-point groups,
+ * Eq. (3)/(4); a point alone beside a wall by Eq. (1)/(2)) along every row
+ * with r = rx, then along every column with r = ry (first-order splitting;
+ * each line paired by the global level index as a single rod is).
+ *
+ * Layout: u holds ny rows of nx values, row-major; element (j, i) is
+ * u(x_{i+1}, y_{j+1}) with hx = 1/(nx+1), hy = 1/(ny+1), so rx = tau/hx^2
+ * and ry = tau/hy^2.  double for GE_FP64, float for GE_FP32.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t nx, ny;     /* interior points per row and per column (>= 1)     */
+    double rx, ry;      /* mesh ratios, > 0 and finite                      */
+    int32_t precision;  /* GE_FP64 or GE_FP32                               */
+    double g_west, g_east, g_south, g_north;   /* wall values (x = 0, x = 1, */
+                                               /* y = 0, y = 1)              */
+} ge_2d_desc;
+
+/* Bytes of device workspace a ge_2d_step_n call needs (a second grid:
+ * nx*ny elements); 0 for an invalid description. */
+size_t ge_2d_workspace_bytes(const ge_2d_desc *desc);
+
+/* Advance the grid u (device, caller-owned, layout above) by nsteps levels
+ * starting at global level step0 >= 0, on `stream` (a hipStream_t, NULL =
+ * the null stream).  workspace: device, ge_2d_workspace_bytes bytes, not
+ * overlapping u.  One launch per level; the call returns once the work is
+ * enqueued and u holds the result when the stream reaches it.  Errors:
+ * GE_ERR_INVALID (bad description, NULL or overlapping buffers, negative
+ * step0/nsteps; nothing enqueued), GE_ERR_UNSUPPORTED (GE_FP32_COMP),
+ * GE_ERR_HIP. */
+ge_status ge_2d_step_n(const ge_2d_desc *desc, void *u, void *workspace, int64_t step0,
+                      int64_t nsteps, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batch of independent rods: the same scheme (Section 2) for every rod, each
  * rod with its own n, r and constant wall values, all advanced by the same
  * levels in one persistent launch that a hipGraph captures.

@@ -11,6 +11,7 @@
 
 #include "ge.h"
 #include "ge_internal.h"
+#include "ge_2d.h"
 #include "ge_kernels.h"
 
 namespace ge {
@@ -498,6 +499,59 @@ ge_status ge_comp_from_fp64(const double *x, float *pair, int64_t n, void *strea
         return fail(GE_ERR_INVALID, "ge_comp_from_fp64: bad arguments");
     hipError_t e = ge::launch_comp_from_fp64(x, pair, n, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? GE_OK : hip_fail(e, "ge_comp_from_fp64");
+}
+
+size_t ge_2d_workspace_bytes(const ge_2d_desc *d)
+{
+    if (!d || d->nx < 1 || d->ny < 1 || d->nx > 0x7fffff00LL || d->ny > 0x7fffff00LL ||
+        (d->precision != ge::kFP64 && d->precision != ge::kFP32))
+        return 0;
+    return (size_t)(d->nx * d->ny) * (size_t)elem_bytes(d->precision);
+}
+
+ge_status ge_2d_step_n(const ge_2d_desc *d, void *u, void *workspace, int64_t step0, int64_t nsteps,
+                      void *stream)
+{
+    if (!d)
+        return fail(GE_ERR_INVALID, "ge_2d_step_n: NULL description");
+    if (d->precision == ge::kFP32C)
+        return fail(GE_ERR_UNSUPPORTED, "ge_2d_step_n: the 2D extension runs in FP64 or FP32");
+    if (d->precision != ge::kFP64 && d->precision != ge::kFP32)
+        return fail(GE_ERR_INVALID, "ge_2d_step_n: precision = %d", d->precision);
+    if (d->nx < 1 || d->ny < 1 || d->nx > 0x7fffff00LL || d->ny > 0x7fffff00LL ||
+        d->nx * d->ny > (1LL << 40))
+        return fail(GE_ERR_INVALID, "ge_2d_step_n: grid %lld x %lld out of range",
+                    (long long)d->nx, (long long)d->ny);
+    if (!(d->rx > 0.0) || !(d->ry > 0.0) || !std::isfinite(d->rx) || !std::isfinite(d->ry))
+        return fail(GE_ERR_INVALID, "ge_2d_step_n: rx, ry must be positive and finite");
+    if (!std::isfinite(d->g_west) || !std::isfinite(d->g_east) || !std::isfinite(d->g_south) ||
+        !std::isfinite(d->g_north))
+        return fail(GE_ERR_INVALID, "ge_2d_step_n: wall values must be finite");
+    if (step0 < 0 || nsteps < 0)
+        return fail(GE_ERR_INVALID, "ge_2d_step_n: step0 and nsteps must be >= 0");
+    if (nsteps == 0)
+        return GE_OK;
+    const size_t bytes = ge_2d_workspace_bytes(d);
+    const uintptr_t a0 = (uintptr_t)u, b0 = (uintptr_t)workspace;
+    if (!u || !workspace || (a0 < b0 + bytes && b0 < a0 + bytes))
+        return fail(GE_ERR_INVALID, "ge_2d_step_n: u and workspace must be distinct, non-overlapping");
+    ge::Grid2dArgs a;
+    a.u = u;
+    a.work = workspace;
+    a.nx = d->nx;
+    a.ny = d->ny;
+    a.step0 = step0;
+    a.nsteps = nsteps;
+    a.rx = d->rx;
+    a.ry = d->ry;
+    a.gw = d->g_west;
+    a.ge = d->g_east;
+    a.gs = d->g_south;
+    a.gn = d->g_north;
+    const hipError_t e = ge::launch_2d(d->precision, a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return ge::set_error(GE_ERR_HIP, "ge_2d_step_n: %s", hipGetErrorString(e));
+    return GE_OK;
 }
 
 }  // extern "C"

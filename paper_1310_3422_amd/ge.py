@@ -35,6 +35,11 @@ class GeBatchDesc(ctypes.Structure):
                 ("tune", _i32), ("sync", _i32)]
 
 
+class Ge2dDesc(ctypes.Structure):
+    _fields_ = [("nx", _i64), ("ny", _i64), ("rx", _dbl), ("ry", _dbl), ("precision", _i32),
+                ("g_west", _dbl), ("g_east", _dbl), ("g_south", _dbl), ("g_north", _dbl)]
+
+
 class GEError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{status_str(status)}: {message}")
@@ -77,6 +82,8 @@ _SIGS = {
     "ge_nn_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, _vp, _vp]),
     "ge_nn_advance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i32, _i32, _dbl,
                                      _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
+    "ge_2d_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Ge2dDesc)]),
+    "ge_2d_step_n": (ctypes.c_int, [ctypes.POINTER(Ge2dDesc), _vp, _vp, _i64, _i64, _vp]),
     "ge_f32_to_f64": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "ge_f64_to_f32": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
 }
@@ -448,3 +455,28 @@ def f64_to_f32(x, out=None, stream=None):
         out = torch.empty(x.numel(), dtype=torch.float32, device=x.device)
     check(lib().ge_f64_to_f32(_ptr(x), _ptr(out), x.numel(), _stream_ptr(stream)))
     return out
+
+
+def ge_2d_desc(nx, ny, rx, ry, precision="fp64", walls=(0.0, 0.0, 0.0, 0.0)):
+    gw, ge_, gs, gn = (float(w) for w in walls)
+    return Ge2dDesc(nx=int(nx), ny=int(ny), rx=float(rx), ry=float(ry),
+                    precision=_prec(precision), g_west=gw, g_east=ge_, g_south=gs, g_north=gn)
+
+
+def step2d_n(u, nx, ny, rx, ry, step0, nsteps, precision="fp64", walls=(0.0, 0.0, 0.0, 0.0),
+             workspace=None, stream=None):
+    """Advance the ny x nx grid ``u`` (contiguous CUDA tensor, row-major,
+    float64 for fp64, float32 for fp32) in place by ``nsteps`` levels of the
+    two-dimensional extension (ge_2d_step_n); walls = (west, east, south,
+    north)."""
+    torch = _torch()
+    d = ge_2d_desc(nx, ny, rx, ry, precision, walls)
+    dtype = torch.float64 if d.precision == GE_FP64 else torch.float32
+    if not u.is_cuda or u.dtype != dtype or not u.is_contiguous() or u.numel() != nx * ny:
+        raise ValueError(f"u must be a contiguous {dtype} CUDA tensor of {nx * ny} values")
+    if workspace is None:
+        workspace = torch.empty(int(lib().ge_2d_workspace_bytes(ctypes.byref(d))),
+                                dtype=torch.uint8, device=u.device)
+    check(lib().ge_2d_step_n(ctypes.byref(d), _ptr(u), _ptr(workspace), int(step0), int(nsteps),
+                            _stream_ptr(stream)))
+    return u

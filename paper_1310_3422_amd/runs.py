@@ -15,6 +15,9 @@
         points, j = 8..19) for the sub-domain scheme (k = 16) and the
         two-point groups at the library's choices
 
+    python -m paper_1310_3422_amd.runs grid2d [--precision fp64] [--levels 200]
+        the two-dimensional extension on a 4096 x 4096 grid (rx = ry = 2)
+
 Each prints JSON lines with the elapsed time of the run (HIP events on its
 stream, after one untimed warm-up run).
 """
@@ -66,6 +69,24 @@ def subdomain(k, precision, levels, schedule=0, depth=0):
             "s": s, "updates_per_s": n * levels / s, "config": plan.config()}
 
 
+def grid2d(precision, levels, nx=4096, ny=4096):
+    import numpy as np
+    import torch
+    from . import ge, inputs
+    fx = inputs.sine_rod(nx, seed=2)
+    y = np.arange(1, ny + 1) / (ny + 1)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    u = torch.from_numpy(np.outer(np.sin(np.pi * y), fx)).to(dt).cuda()
+    ws = torch.empty_like(u)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = _timed(torch, stream, lambda: ge.step2d_n(u, nx, ny, 2.0, 2.0, 0, levels,
+                                                      precision=precision, workspace=ws,
+                                                      stream=stream))
+    return {"workload": "grid2d", "precision": precision, "nx": nx, "ny": ny, "levels": levels,
+            "s": s, "updates_per_s": nx * ny * levels / s}
+
+
 def occupancy(precision, levels):
     import torch
     from . import ge, inputs
@@ -115,6 +136,9 @@ def main(argv=None):
     s.add_argument("--levels", type=int, default=960)
     s.add_argument("--schedule", type=int, default=0, choices=[0, 1, 2])
     s.add_argument("--depth", type=int, default=0)
+    g2 = sub.add_parser("grid2d")
+    g2.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    g2.add_argument("--levels", type=int, default=200)
     o = sub.add_parser("occupancy")
     o.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
     o.add_argument("--levels", type=int, default=1200)
@@ -127,7 +151,9 @@ def main(argv=None):
         for line in occupancy(args.precision, args.levels):
             print(json.dumps(line), flush=True)
         return 0
-    if args.cmd == "batch":
+    if args.cmd == "grid2d":
+        out = grid2d(args.precision, args.levels)
+    elif args.cmd == "batch":
         out = batch(args.precision, args.levels)
     else:
         out = subdomain(args.k, args.precision, args.levels, args.schedule, args.depth)

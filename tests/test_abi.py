@@ -338,3 +338,44 @@ def test_subdomain_library_choice(prec, k, want):
     ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w), ctypes.byref(hal))
     assert (d.value, ge.lib().ge_plan_schedule(h)) == want
     ge.lib().ge_destroy(h)
+
+
+def _d2(**kw):
+    d = dict(nx=10, ny=7, rx=1.0, ry=2.0, precision=0)
+    d.update(kw)
+    return ge.Ge2dDesc(**d)
+
+
+def test_2d_workspace_bytes():
+    assert ge.lib().ge_2d_workspace_bytes(ctypes.byref(_d2())) == 560
+    assert ge.lib().ge_2d_workspace_bytes(ctypes.byref(_d2(precision=1))) == 280
+    assert ge.lib().ge_2d_workspace_bytes(ctypes.byref(_d2(nx=0))) == 0
+    assert ge.lib().ge_2d_workspace_bytes(None) == 0
+
+
+@pytest.mark.parametrize("kw,args,status", [
+    (dict(nx=0), {}, ge.GE_ERR_INVALID),
+    (dict(ny=-1), {}, ge.GE_ERR_INVALID),
+    (dict(rx=0.0), {}, ge.GE_ERR_INVALID),
+    (dict(ry=float("inf")), {}, ge.GE_ERR_INVALID),
+    (dict(g_north=float("nan")), {}, ge.GE_ERR_INVALID),
+    (dict(precision=2), {}, ge.GE_ERR_UNSUPPORTED),
+    (dict(precision=7), {}, ge.GE_ERR_INVALID),
+    (dict(nx=1 << 32), {}, ge.GE_ERR_INVALID),
+    ({}, dict(step0=-1), ge.GE_ERR_INVALID),
+    ({}, dict(nsteps=-2), ge.GE_ERR_INVALID),
+    ({}, dict(ws=0x100000 + 8), ge.GE_ERR_INVALID),     # overlaps u
+    ({}, dict(u=None), ge.GE_ERR_INVALID),
+])
+def test_2d_rejects(kw, args, status):
+    """Argument errors return before anything is enqueued (no device needed)."""
+    a = dict(u=0x100000, ws=0x200000, step0=0, nsteps=3)
+    a.update(args)
+    st = ge.lib().ge_2d_step_n(ctypes.byref(_d2(**kw)), ctypes.c_void_p(a["u"]) if a["u"] else None,
+                               ctypes.c_void_p(a["ws"]), a["step0"], a["nsteps"], None)
+    assert st == status, ge.last_error()
+
+
+def test_2d_zero_levels_is_a_no_op():
+    assert ge.lib().ge_2d_step_n(ctypes.byref(_d2()), ctypes.c_void_p(0x100000),
+                                 ctypes.c_void_p(0x200000), 0, 0, None) == ge.GE_OK

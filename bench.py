@@ -13,8 +13,10 @@ Prints one JSON line.  Beside the headline value it carries
   cpu_baseline : the CPU oracle (all host cores, one barrier per level) on a
                  bounded number of levels of the same rod;
   extra        : the depth-1 streaming sweep against HBM bandwidth, the
-                 compensated FP32 form on the same rod, and a sampled parity
-                 check of the timed result against the oracle;
+                 compensated FP32 form on the same rod, a sampled parity
+                 check of the timed result against the oracle, the
+                 sub-domain scheme (k = 16), the 4096-rod batch, the 2D
+                 extension on a 4096 x 4096 grid and the surrogate;
   paper_e2_shape : the paper's timing runs (about 2.6e5 nodes, 20 to 1200
                  time rows) on the GPU and on the CPU oracle.
 """

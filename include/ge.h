@@ -190,6 +190,9 @@ typedef struct {
     int32_t precision;  /* GE_FP64 or GE_FP32                               */
     double g_west, g_east, g_south, g_north;   /* wall values (x = 0, x = 1, */
                                                /* y = 0, y = 1)              */
+    int32_t depth;      /* levels fused per launch: 1, 2 or 4 (a halo of 2   */
+                        /* points per level and side is recomputed); 0 =     */
+                        /* library choice.  Changes no bits of the result.   */
 } ge_2d_desc;
 
 /* Bytes of device workspace a ge_2d_step_n call needs (a second grid:
@@ -199,11 +202,11 @@ size_t ge_2d_workspace_bytes(const ge_2d_desc *desc);
 /* Advance the grid u (device, caller-owned, layout above) by nsteps levels
  * starting at global level step0 >= 0, on `stream` (a hipStream_t, NULL =
  * the null stream).  workspace: device, ge_2d_workspace_bytes bytes, not
- * overlapping u.  One launch per level; the call returns once the work is
+ * overlapping u.  One launch per `depth` levels; the call returns once the work is
  * enqueued and u holds the result when the stream reaches it.  Errors:
  * GE_ERR_INVALID (bad description, NULL or overlapping buffers, negative
- * step0/nsteps; nothing enqueued), GE_ERR_UNSUPPORTED (GE_FP32_COMP),
- * GE_ERR_HIP. */
+ * step0/nsteps, depth not 0, 1, 2 or 4; nothing enqueued),
+ * GE_ERR_UNSUPPORTED (GE_FP32_COMP), GE_ERR_HIP. */
 ge_status ge_2d_step_n(const ge_2d_desc *desc, void *u, void *workspace, int64_t step0,
                       int64_t nsteps, void *stream);
 

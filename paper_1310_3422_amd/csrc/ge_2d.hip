@@ -8,15 +8,18 @@
 // single rod is).
 //
 // A one-dimensional level is explicit: a point's new value depends on old
-// values at most two places away along its line.  So one launch advances
-// one level of a tile of 16 (FP64) or 32 (FP32) rows by 128 columns: the input tile with two
-// points of halo on every side goes from HBM to LDS (coalesced rows), the
-// x-level runs on the tile's rows plus two halo rows above and below and
-// overwrites the tile in place (after a barrier), and the y-level reads it
-// and writes straight back to HBM.  Per level the grid is read and written
-// once: 16 bytes per point in FP64, HBM-bound.  Tiles are dealt to the XCDs
-// in contiguous runs, so a tile's neighbours (which read the same halo
-// lines) mostly run on the same L2 at about the same time.
+// values at most two places away along its line.  So a launch advances D
+// levels (D = 1, 2 or 4) of a tile of 128 columns by 16 (FP64) or 32 (FP32)
+// rows: the tile with a halo of 2D points on every side goes from HBM to LDS
+// (coalesced rows, every load of a thread issued before the first is used);
+// each level runs the x-level on the still-valid region (which loses two
+// points of width per side), overwriting it in place after a barrier, then
+// the y-level likewise (two rows per side); the last y-level writes the tile
+// straight to HBM.  Per launch the grid is read and written once: 16/D bytes
+// per point and level in FP64.  Tiles are dealt to the XCDs in contiguous
+// runs, so neighbours that re-read a tile's halo lines mostly run on the
+// same L2 at about the same time.  Every point is advanced by the same
+// operations whatever D is, so the depth changes no bits.
 //
 // Walls are constant in time (west, east, south, north); the values beside
 // a wall read the wall, which sits in the tile's halo cells.
@@ -31,18 +34,17 @@ namespace {
 
 constexpr int kTI = 128;            // columns per tile
 constexpr int kThreads = 256;
-constexpr int kAW = kTI + 4;        // tile row, with the halo
 
-// Rows per tile: 16 in FP64 (21 KB of LDS, more tiles resident per CU: 12%
-// faster than 32 rows on a 4096^2 grid, while the extra halo rows hit in
-// L2), 32 in FP32 (3% faster than 16).
-template <typename T> struct Tile {
+// Rows per tile: 16 in FP64 (less LDS, more tiles resident per CU: 12%
+// faster than 32 rows at D = 1 on a 4096^2 grid, while the extra halo rows
+// hit in L2), 32 in FP32 (3% faster than 16).
+template <typename T, int D> struct Tile {
     static constexpr int TJ = sizeof(T) == 8 ? 16 : 32;
-    static constexpr int AH = TJ + 4;
-    static constexpr int LPer = (AH * kAW + kThreads - 1) / kThreads;   // loads per thread
-    static constexpr int XPer = AH * kTI / kThreads;                    // x-level values
-    static constexpr int YPer = TJ * kTI / kThreads;                    // y-level values
-    static_assert(AH * kTI % kThreads == 0 && TJ * kTI % kThreads == 0, "whole rows per block");
+    static constexpr int H = 2 * D;                  // halo per side
+    static constexpr int AW = kTI + 2 * H, AH = TJ + 2 * H;
+    static constexpr int LPer = (AH * AW + kThreads - 1) / kThreads;              // loads
+    static constexpr int XPer = (AH * (AW - 4) + kThreads - 1) / kThreads;        // x cells
+    static constexpr int YPer = ((AH - 4) * (AW - 4) + kThreads - 1) / kThreads;  // y cells
 };
 
 template <typename T> struct Line {
@@ -71,75 +73,112 @@ __device__ __forceinline__ T level1d(T um2, T um1, T u0, T up1, T up2, int e, in
     else return u0 + fmaf(c.c2, Dq, c.c1 * De);
 }
 
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void level2d_kernel(const T *__restrict__ in,
                                                            T *__restrict__ out, int nx, int ny,
-                                                           int tiles_x, int ntiles, int p,
+                                                           int tiles_x, int ntiles, int p0,
                                                            Line<T> cx, Line<T> cy, T gw, T ge_,
                                                            T gs, T gn)
 {
-    using G = Tile<T>;
-    constexpr int kTJ = G::TJ, kAH = G::AH, kLPer = G::LPer, kXPer = G::XPer, kYPer = G::YPer;
-    __shared__ T A[kAH][kAW];     // the tile with its halo; after the x-level, that level
+    using G = Tile<T, D>;
+    constexpr int TJ = G::TJ, H = G::H, AW = G::AW, AH = G::AH;
+    __shared__ T A[AH][AW];       // the tile and its halo, advanced in place
     const int per = gridDim.x / 8;
     const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-aware
     if (t >= ntiles)
         return;
-    const int i0 = (t % tiles_x) * kTI, j0 = (t / tiles_x) * kTJ;
+    const int jb = (t / tiles_x) * TJ - H, ib = (t % tiles_x) * kTI - H;   // cell (0, 0)
     const int tid = threadIdx.x;
-    // HBM -> LDS, every load issued before the first is used; cells past a
-    // west/east wall hold the wall
-    T v[kLPer];
+    // HBM -> LDS; cells on a wall hold it, cells past one are never read
+    T v[G::LPer];
 #pragma unroll
-    for (int q = 0; q < kLPer; ++q) {
+    for (int q = 0; q < G::LPer; ++q) {
         const int k = tid + q * kThreads;
-        const int r = k / kAW, c = k % kAW;
-        const int j = j0 - 2 + r, i = i0 - 2 + c;
+        const int j = jb + k / AW, i = ib + k % AW;
         T x = T(0);
-        if (k < kAH * kAW && j >= 0 && j < ny) {
-            if (i >= 0 && i < nx) x = in[(int64_t)j * nx + i];
-            else if (i == -1) x = gw;
-            else if (i == nx) x = ge_;
+        if (k < AH * AW) {
+            if (j == -1) x = gs;
+            else if (j == ny) x = gn;
+            else if (j >= 0 && j < ny) {
+                if (i >= 0 && i < nx) x = in[(int64_t)j * nx + i];
+                else if (i == -1) x = gw;
+                else if (i == nx) x = ge_;
+            }
         }
         v[q] = x;
     }
 #pragma unroll
-    for (int q = 0; q < kLPer; ++q) {
+    for (int q = 0; q < G::LPer; ++q) {
         const int k = tid + q * kThreads;
-        if (k < kAH * kAW) A[k / kAW][k % kAW] = v[q];
-    }
-    __syncthreads();
-    // x-level on rows j0-2 .. j0+kTJ+1, held in registers until every
-    // thread has read its old values; rows past a south/north wall hold it
-    T x[kXPer];
-#pragma unroll
-    for (int q = 0; q < kXPer; ++q) {
-        const int k = tid + q * kThreads;
-        const int r = k / kTI, c = k % kTI;
-        const int j = j0 - 2 + r, i = i0 + c;
-        T y = T(0);
-        if (j == -1) y = gs;
-        else if (j == ny) y = gn;
-        else if (j >= 0 && j < ny && i < nx)
-            y = level1d(A[r][c], A[r][c + 1], A[r][c + 2], A[r][c + 3], A[r][c + 4], i, nx, p, cx);
-        x[q] = y;
+        if (k < AH * AW) A[k / AW][k % AW] = v[q];
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kXPer; ++q) {
-        const int k = tid + q * kThreads;
-        A[k / kTI][k % kTI + 2] = x[q];
-    }
-    __syncthreads();
-    // y-level on the tile's rows, straight to HBM
+    for (int l = 0; l < D; ++l) {
+        const int p = (p0 + l) & 1;
+        // valid before this level: rows [2l, AH-2l), columns [2l, AW-2l)
+        const int w = AW - 4 * l - 4;                 // columns [2l+2, AW-2l-2)
+        const int hx = AH - 4 * l, hy = AH - 4 * l - 4;
+        // x-level on every valid row; new values held in registers until
+        // every thread has read its old ones
+        T xv[G::XPer];
 #pragma unroll
-    for (int q = 0; q < kYPer; ++q) {
-        const int k = tid + q * kThreads;
-        const int r = k / kTI, c = k % kTI + 2;
-        const int j = j0 + r, i = i0 + c - 2;
-        if (j < ny && i < nx)
-            out[(int64_t)j * nx + i] = level1d(A[r][c], A[r + 1][c], A[r + 2][c], A[r + 3][c],
-                                               A[r + 4][c], j, ny, p, cy);
+        for (int q = 0; q < G::XPer; ++q) {
+            const int k = tid + q * kThreads;
+            T y = T(0);
+            if (k < w * hx) {
+                const int r = 2 * l + k / w, c = 2 * l + 2 + k % w;
+                const int j = jb + r, i = ib + c;
+                y = A[r][c];
+                if (j >= 0 && j < ny && i >= 0 && i < nx)
+                    y = level1d(A[r][c - 2], A[r][c - 1], y, A[r][c + 1], A[r][c + 2], i, nx, p, cx);
+            }
+            xv[q] = y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < G::XPer; ++q) {
+            const int k = tid + q * kThreads;
+            if (k < w * hx) A[2 * l + k / w][2 * l + 2 + k % w] = xv[q];
+        }
+        __syncthreads();
+        if (l == D - 1) {
+            // the last y-level covers exactly the tile: straight to HBM
+#pragma unroll
+            for (int q = 0; q < G::YPer; ++q) {
+                const int k = tid + q * kThreads;
+                if (k < w * hy) {
+                    const int r = 2 * l + 2 + k / w, c = 2 * l + 2 + k % w;
+                    const int j = jb + r, i = ib + c;
+                    if (j < ny && i < nx)
+                        out[(int64_t)j * nx + i] = level1d(A[r - 2][c], A[r - 1][c], A[r][c],
+                                                           A[r + 1][c], A[r + 2][c], j, ny, p, cy);
+                }
+            }
+        } else {
+            T yv[G::YPer];
+#pragma unroll
+            for (int q = 0; q < G::YPer; ++q) {
+                const int k = tid + q * kThreads;
+                T y = T(0);
+                if (k < w * hy) {
+                    const int r = 2 * l + 2 + k / w, c = 2 * l + 2 + k % w;
+                    const int j = jb + r, i = ib + c;
+                    y = A[r][c];
+                    if (j >= 0 && j < ny && i >= 0 && i < nx)
+                        y = level1d(A[r - 2][c], A[r - 1][c], y, A[r + 1][c], A[r + 2][c], j, ny, p,
+                                    cy);
+                }
+                yv[q] = y;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < G::YPer; ++q) {
+                const int k = tid + q * kThreads;
+                if (k < w * hy) A[2 * l + 2 + k / w][2 * l + 2 + k % w] = yv[q];
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -149,26 +188,39 @@ template <typename T> Line<T> line_coef(double r)
                    (T)(r / (1.0 + r))};
 }
 
+template <typename T, int D>
+hipError_t launch_levels(const T *src, T *dst, const Grid2dArgs &a, int64_t m, hipStream_t stream)
+{
+    const int64_t tx = (a.nx + kTI - 1) / kTI, ty = (a.ny + Tile<T, D>::TJ - 1) / Tile<T, D>::TJ;
+    const int64_t ntiles = tx * ty, grid = (ntiles + 7) / 8 * 8;
+    hipLaunchKernelGGL((level2d_kernel<T, D>), dim3((unsigned)grid), dim3(kThreads), 0, stream, src,
+                       dst, (int)a.nx, (int)a.ny, (int)tx, (int)ntiles, (int)(m & 1),
+                       line_coef<T>(a.rx), line_coef<T>(a.ry), (T)a.gw, (T)a.ge, (T)a.gs, (T)a.gn);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_2d_t(const Grid2dArgs &a, hipStream_t stream)
 {
-    const int64_t tx = (a.nx + kTI - 1) / kTI, ty = (a.ny + Tile<T>::TJ - 1) / Tile<T>::TJ;
-    const int64_t ntiles = tx * ty, grid = (ntiles + 7) / 8 * 8;
-    const Line<T> cx = line_coef<T>(a.rx), cy = line_coef<T>(a.ry);
     const T *src = static_cast<const T *>(a.u);
     T *dst = static_cast<T *>(a.work);
-    for (int64_t s = 0; s < a.nsteps; ++s) {
-        hipLaunchKernelGGL((level2d_kernel<T>), dim3((unsigned)grid), dim3(kThreads), 0, stream,
-                           src, dst, (int)a.nx, (int)a.ny, (int)tx, (int)ntiles,
-                           (int)((a.step0 + s) & 1), cx, cy, (T)a.gw, (T)a.ge, (T)a.gs, (T)a.gn);
-        const hipError_t e = hipGetLastError();
+    int64_t launches = 0;
+    for (int64_t s = 0; s < a.nsteps;) {
+        // D levels per launch while D remain, then single levels
+        const int d = a.nsteps - s >= a.depth ? a.depth : 1;
+        hipError_t e;
+        if (d == 4) e = launch_levels<T, 4>(src, dst, a, a.step0 + s, stream);
+        else if (d == 2) e = launch_levels<T, 2>(src, dst, a, a.step0 + s, stream);
+        else e = launch_levels<T, 1>(src, dst, a, a.step0 + s, stream);
         if (e != hipSuccess) return e;
+        s += d;
+        ++launches;
         T *t = const_cast<T *>(src);
         src = dst;
         dst = t;
     }
-    // after an odd number of levels the result sits in the workspace
-    if (a.nsteps % 2 == 1)
+    // after an odd number of launches the result sits in the workspace
+    if (launches % 2 == 1)
         return hipMemcpyAsync(a.u, a.work, (size_t)(a.nx * a.ny) * sizeof(T),
                               hipMemcpyDeviceToDevice, stream);
     return hipSuccess;
@@ -180,7 +232,8 @@ hipError_t launch_2d(int prec, const Grid2dArgs &a, hipStream_t stream)
 {
     const int64_t tiles = ((a.nx + kTI - 1) / kTI) * ((a.ny + 15) / 16);
     // indices inside a launch are 32-bit: rows and columns below 2^31
-    if (a.nx < 1 || a.ny < 1 || a.nx > 0x7fffff00LL || a.ny > 0x7fffff00LL || tiles > 0x7ffffff0LL)
+    if (a.nx < 1 || a.ny < 1 || a.nx > 0x7fffff00LL || a.ny > 0x7fffff00LL || tiles > 0x7ffffff0LL ||
+        (a.depth != 1 && a.depth != 2 && a.depth != 4))
         return hipErrorInvalidValue;
     if (prec == kFP64) return launch_2d_t<double>(a, stream);
     if (prec == kFP32) return launch_2d_t<float>(a, stream);

@@ -501,6 +501,12 @@ ge_status ge_comp_from_fp64(const double *x, float *pair, int64_t n, void *strea
     return e == hipSuccess ? GE_OK : hip_fail(e, "ge_comp_from_fp64");
 }
 
+// Levels per launch of the 2D extension when the caller leaves it to the
+// library: measured on MI355X (4096^2 points), two fused levels ran as fast
+// as one in FP64 and 15% slower in FP32, four 17-30% slower (the halo
+// recompute and two barriers per level outweigh the saved HBM traffic).
+constexpr int kDepth2d = 1;
+
 size_t ge_2d_workspace_bytes(const ge_2d_desc *d)
 {
     if (!d || d->nx < 1 || d->ny < 1 || d->nx > 0x7fffff00LL || d->ny > 0x7fffff00LL ||
@@ -529,6 +535,8 @@ ge_status ge_2d_step_n(const ge_2d_desc *d, void *u, void *workspace, int64_t st
         return fail(GE_ERR_INVALID, "ge_2d_step_n: wall values must be finite");
     if (step0 < 0 || nsteps < 0)
         return fail(GE_ERR_INVALID, "ge_2d_step_n: step0 and nsteps must be >= 0");
+    if (d->depth != 0 && d->depth != 1 && d->depth != 2 && d->depth != 4)
+        return fail(GE_ERR_INVALID, "ge_2d_step_n: depth = %d, need 0, 1, 2 or 4", d->depth);
     if (nsteps == 0)
         return GE_OK;
     const size_t bytes = ge_2d_workspace_bytes(d);
@@ -548,6 +556,7 @@ ge_status ge_2d_step_n(const ge_2d_desc *d, void *u, void *workspace, int64_t st
     a.ge = d->g_east;
     a.gs = d->g_south;
     a.gn = d->g_north;
+    a.depth = d->depth != 0 ? d->depth : kDepth2d;
     const hipError_t e = ge::launch_2d(d->precision, a, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return ge::set_error(GE_ERR_HIP, "ge_2d_step_n: %s", hipGetErrorString(e));

@@ -37,7 +37,8 @@ class GeBatchDesc(ctypes.Structure):
 
 class Ge2dDesc(ctypes.Structure):
     _fields_ = [("nx", _i64), ("ny", _i64), ("rx", _dbl), ("ry", _dbl), ("precision", _i32),
-                ("g_west", _dbl), ("g_east", _dbl), ("g_south", _dbl), ("g_north", _dbl)]
+                ("g_west", _dbl), ("g_east", _dbl), ("g_south", _dbl), ("g_north", _dbl),
+                ("depth", _i32)]
 
 
 class GEError(RuntimeError):
@@ -457,20 +458,21 @@ def f64_to_f32(x, out=None, stream=None):
     return out
 
 
-def ge_2d_desc(nx, ny, rx, ry, precision="fp64", walls=(0.0, 0.0, 0.0, 0.0)):
+def ge_2d_desc(nx, ny, rx, ry, precision="fp64", walls=(0.0, 0.0, 0.0, 0.0), depth=0):
     gw, ge_, gs, gn = (float(w) for w in walls)
     return Ge2dDesc(nx=int(nx), ny=int(ny), rx=float(rx), ry=float(ry),
-                    precision=_prec(precision), g_west=gw, g_east=ge_, g_south=gs, g_north=gn)
+                    precision=_prec(precision), g_west=gw, g_east=ge_, g_south=gs, g_north=gn,
+                    depth=int(depth))
 
 
 def step2d_n(u, nx, ny, rx, ry, step0, nsteps, precision="fp64", walls=(0.0, 0.0, 0.0, 0.0),
-             workspace=None, stream=None):
+             workspace=None, stream=None, depth=0):
     """Advance the ny x nx grid ``u`` (contiguous CUDA tensor, row-major,
     float64 for fp64, float32 for fp32) in place by ``nsteps`` levels of the
     two-dimensional extension (ge_2d_step_n); walls = (west, east, south,
     north)."""
     torch = _torch()
-    d = ge_2d_desc(nx, ny, rx, ry, precision, walls)
+    d = ge_2d_desc(nx, ny, rx, ry, precision, walls, depth)
     dtype = torch.float64 if d.precision == GE_FP64 else torch.float32
     if not u.is_cuda or u.dtype != dtype or not u.is_contiguous() or u.numel() != nx * ny:
         raise ValueError(f"u must be a contiguous {dtype} CUDA tensor of {nx * ny} values")

@@ -69,7 +69,7 @@ def subdomain(k, precision, levels, schedule=0, depth=0):
             "s": s, "updates_per_s": n * levels / s, "config": plan.config()}
 
 
-def grid2d(precision, levels, nx=4096, ny=4096):
+def grid2d(precision, levels, nx=4096, ny=4096, depth=0):
     import numpy as np
     import torch
     from . import ge, inputs
@@ -82,9 +82,9 @@ def grid2d(precision, levels, nx=4096, ny=4096):
     with torch.cuda.stream(stream):
         s = _timed(torch, stream, lambda: ge.step2d_n(u, nx, ny, 2.0, 2.0, 0, levels,
                                                       precision=precision, workspace=ws,
-                                                      stream=stream))
+                                                      stream=stream, depth=depth))
     return {"workload": "grid2d", "precision": precision, "nx": nx, "ny": ny, "levels": levels,
-            "s": s, "updates_per_s": nx * ny * levels / s}
+            "depth": depth, "s": s, "updates_per_s": nx * ny * levels / s}
 
 
 def occupancy(precision, levels):
@@ -139,6 +139,7 @@ def main(argv=None):
     g2 = sub.add_parser("grid2d")
     g2.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     g2.add_argument("--levels", type=int, default=200)
+    g2.add_argument("--depth", type=int, default=0, choices=[0, 1, 2, 4])
     o = sub.add_parser("occupancy")
     o.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
     o.add_argument("--levels", type=int, default=1200)
@@ -152,7 +153,7 @@ def main(argv=None):
             print(json.dumps(line), flush=True)
         return 0
     if args.cmd == "grid2d":
-        out = grid2d(args.precision, args.levels)
+        out = grid2d(args.precision, args.levels, depth=args.depth)
     elif args.cmd == "batch":
         out = batch(args.precision, args.levels)
     else:

@@ -362,6 +362,7 @@ def test_2d_workspace_bytes():
     (dict(precision=2), {}, ge.GE_ERR_UNSUPPORTED),
     (dict(precision=7), {}, ge.GE_ERR_INVALID),
     (dict(nx=1 << 32), {}, ge.GE_ERR_INVALID),
+    (dict(depth=3), {}, ge.GE_ERR_INVALID),
     ({}, dict(step0=-1), ge.GE_ERR_INVALID),
     ({}, dict(nsteps=-2), ge.GE_ERR_INVALID),
     ({}, dict(ws=0x100000 + 8), ge.GE_ERR_INVALID),     # overlaps u

@@ -104,3 +104,36 @@ def test_unit_square_sine_decays():
     got = run(u0, 1.0, 1.0, steps)
     exact = np.exp(-2 * np.pi ** 2 * t) * u0
     assert np.abs(got - exact).max() < 0.05 * (1 - np.exp(-2 * np.pi ** 2 * t))
+
+
+@pytest.mark.parametrize("nx,ny", [(50001, 1), (1, 3001), (3, 2500)])
+def test_long_thin_grids(nx, ny):
+    """One long row (hundreds of tiles side by side, every column a single
+    point between the south and north walls), one long column, and a
+    three-column strip."""
+    u0 = grid(nx, ny, nx + ny)
+    got = run(u0, 2.2, 0.9, 3, step0=1, walls=WALLS)
+    want = oracle.step2d_n(u0, 2.2, 0.9, 3, step0=1, walls=WALLS)
+    assert rel_l2(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (5, 3), (129, 17), (300, 70), (1000, 1)])
+@pytest.mark.parametrize("nsteps", [1, 5, 8])
+def test_depths_give_the_same_bits(precision, nx, ny, nsteps):
+    """Fusing 2 or 4 levels per launch recomputes the halo with the same
+    operations: every depth, with a remainder of single levels, gives the
+    bits of one level per launch."""
+    u0 = grid(nx, ny, 17)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    outs = []
+    for depth in (1, 2, 4):
+        u = torch.from_numpy(u0.copy()).to(dt).cuda()
+        ge.step2d_n(u, nx, ny, 1.4, 2.6, 3, nsteps, precision=precision, walls=WALLS, depth=depth)
+        torch.cuda.synchronize()
+        outs.append(u.cpu().numpy())
+    np.testing.assert_array_equal(outs[1], outs[0])
+    np.testing.assert_array_equal(outs[2], outs[0])
+    if precision == "fp64":
+        want = oracle.step2d_n(u0, 1.4, 2.6, nsteps, step0=3, walls=WALLS)
+        assert rel_l2(outs[0].astype(np.float64), want) < 1e-12

@@ -9,43 +9,27 @@
 //
 // A one-dimensional level is explicit: a point's new value depends on old
 // values at most two places away along its line.  So a launch advances D
-// levels (D = 1, 2 or 4) of a tile of 128 columns by 16 (FP64) or 32 (FP32)
-// rows: the tile with a halo of 2D points on every side goes from HBM to LDS
-// (coalesced rows, every load of a thread issued before the first is used);
-// each level runs the x-level on the still-valid region (which loses two
-// points of width per side), overwriting it in place after a barrier, then
-// the y-level likewise (two rows per side); the last y-level writes the tile
-// straight to HBM.  Per launch the grid is read and written once: 16/D bytes
-// per point and level in FP64.  Tiles are dealt to the XCDs in contiguous
-// runs, so neighbours that re-read a tile's halo lines mostly run on the
-// same L2 at about the same time.  Every point is advanced by the same
-// operations whatever D is, so the depth changes no bits.
+// levels (D = 1, 2 or 4) of a strip of columns held in registers, one column
+// per lane (see level2d_reg_kernel): the x-level's neighbours come from the
+// lanes beside it by DPP shifts, the y-level's from the lane's own rows, and
+// the valid lanes and rows shrink by two per side and level (a halo of 2D
+// lanes and rows, recomputed).  Per launch the grid is read and written
+// once: 16/D bytes per point and level in FP64.  Every point is advanced by
+// the same operations whatever D is, so the depth changes no bits.
 //
 // Walls are constant in time (west, east, south, north); the values beside
-// a wall read the wall, which sits in the tile's halo cells.
+// a wall read the wall, which a halo lane or row holds.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "ge_2d.h"
 #include "ge_kernels.h"
+#include "ge_level.h"
 
 namespace ge {
 namespace {
 
-constexpr int kTI = 128;            // columns per tile
-constexpr int kThreads = 256;
-
-// Rows per tile: 16 in FP64 (less LDS, more tiles resident per CU: 12%
-// faster than 32 rows at D = 1 on a 4096^2 grid, while the extra halo rows
-// hit in L2), 32 in FP32 (3% faster than 16).
-template <typename T, int D> struct Tile {
-    static constexpr int TJ = sizeof(T) == 8 ? 16 : 32;
-    static constexpr int H = 2 * D;                  // halo per side
-    static constexpr int AW = kTI + 2 * H, AH = TJ + 2 * H;
-    static constexpr int LPer = (AH * AW + kThreads - 1) / kThreads;              // loads
-    static constexpr int XPer = (AH * (AW - 4) + kThreads - 1) / kThreads;        // x cells
-    static constexpr int YPer = ((AH - 4) * (AW - 4) + kThreads - 1) / kThreads;  // y cells
-};
+constexpr int kThreads = 256;       // four waves, four column strips
 
 template <typename T> struct Line {
     T c1, c2, cs;   // (r+r^2)/(1+2r), r^2/(1+2r), r/(1+r)
@@ -73,112 +57,94 @@ __device__ __forceinline__ T level1d(T um2, T um1, T u0, T up1, T up2, int e, in
     else return u0 + fmaf(c.c2, Dq, c.c1 * De);
 }
 
+// Register form.  Lane l of a wave holds column c0 - 2D + l for rows
+// r0 - 2D .. r0 + R + 2D - 1 (walls where they fall, zero past them); each
+// level takes the x-level's neighbours from the lanes beside it (DPP shifts
+// by one and two lanes; the edge lanes are halo) and the y-level's from the
+// lane's own registers.  The valid lanes and rows shrink by two per side
+// and level; after D levels lanes 2D..63-2D write their column's R rows.
+// No LDS and no barrier: every load of a lane is issued at once.
+using dev::kWave;
+
+template <typename T>
+__device__ __forceinline__ T shr1(T v) { return dev::from_left_open(v); }    // lane l-1
+template <typename T>
+__device__ __forceinline__ T shl1(T v) { return dev::from_right_open(v); }   // lane l+1
+
+template <int D> struct RegTile {
+    static constexpr int R = D == 1 ? 32 : D == 2 ? 24 : 16;   // output rows per wave
+    static constexpr int H = 2 * D;                            // halo lanes / rows per side
+    static constexpr int N = R + 2 * H;                        // rows held
+    static constexpr int COLS = kWave - 2 * H;                 // output columns per wave
+};
+
 template <typename T, int D>
-__global__ __launch_bounds__(kThreads) void level2d_kernel(const T *__restrict__ in,
-                                                           T *__restrict__ out, int nx, int ny,
-                                                           int tiles_x, int ntiles, int p0,
-                                                           Line<T> cx, Line<T> cy, T gw, T ge_,
-                                                           T gs, T gn)
+__global__ __launch_bounds__(kThreads) void level2d_reg_kernel(const T *__restrict__ in,
+                                                               T *__restrict__ out, int nx, int ny,
+                                                               int strips, int ntiles, int p0,
+                                                               Line<T> cx, Line<T> cy, T gw,
+                                                               T ge_, T gs, T gn)
 {
-    using G = Tile<T, D>;
-    constexpr int TJ = G::TJ, H = G::H, AW = G::AW, AH = G::AH;
-    __shared__ T A[AH][AW];       // the tile and its halo, advanced in place
+    using G = RegTile<D>;
+    constexpr int R = G::R, H = G::H, N = G::N;
     const int per = gridDim.x / 8;
-    const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-aware
+    const int b = (blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-aware
+    const int t = b * (kThreads / kWave) + threadIdx.x / kWave;   // this wave's tile
     if (t >= ntiles)
         return;
-    const int jb = (t / tiles_x) * TJ - H, ib = (t % tiles_x) * kTI - H;   // cell (0, 0)
-    const int tid = threadIdx.x;
-    // HBM -> LDS; cells on a wall hold it, cells past one are never read
-    T v[G::LPer];
+    const int lane = threadIdx.x % kWave;
+    const int i = (t % strips) * G::COLS - H + lane;
+    const int jb = (t / strips) * R - H;
+    const bool col_in = i >= 0 && i < nx;
+    T u[N];
 #pragma unroll
-    for (int q = 0; q < G::LPer; ++q) {
-        const int k = tid + q * kThreads;
-        const int j = jb + k / AW, i = ib + k % AW;
+    for (int q = 0; q < N; ++q) {
+        const int j = jb + q;
         T x = T(0);
-        if (k < AH * AW) {
-            if (j == -1) x = gs;
-            else if (j == ny) x = gn;
-            else if (j >= 0 && j < ny) {
-                if (i >= 0 && i < nx) x = in[(int64_t)j * nx + i];
-                else if (i == -1) x = gw;
-                else if (i == nx) x = ge_;
-            }
+        if (j == -1) x = gs;
+        else if (j == ny) x = gn;
+        else if (j >= 0 && j < ny) {
+            if (col_in) x = in[(int64_t)j * nx + i];
+            else if (i == -1) x = gw;
+            else if (i == nx) x = ge_;
         }
-        v[q] = x;
+        u[q] = x;
     }
-#pragma unroll
-    for (int q = 0; q < G::LPer; ++q) {
-        const int k = tid + q * kThreads;
-        if (k < AH * AW) A[k / AW][k % AW] = v[q];
-    }
-    __syncthreads();
 #pragma unroll
     for (int l = 0; l < D; ++l) {
         const int p = (p0 + l) & 1;
-        // valid before this level: rows [2l, AH-2l), columns [2l, AW-2l)
-        const int w = AW - 4 * l - 4;                 // columns [2l+2, AW-2l-2)
-        const int hx = AH - 4 * l, hy = AH - 4 * l - 4;
-        // x-level on every valid row; new values held in registers until
-        // every thread has read its old ones
-        T xv[G::XPer];
+        // x-level on rows [2l, N - 2l)
 #pragma unroll
-        for (int q = 0; q < G::XPer; ++q) {
-            const int k = tid + q * kThreads;
-            T y = T(0);
-            if (k < w * hx) {
-                const int r = 2 * l + k / w, c = 2 * l + 2 + k % w;
-                const int j = jb + r, i = ib + c;
-                y = A[r][c];
-                if (j >= 0 && j < ny && i >= 0 && i < nx)
-                    y = level1d(A[r][c - 2], A[r][c - 1], y, A[r][c + 1], A[r][c + 2], i, nx, p, cx);
-            }
-            xv[q] = y;
+        for (int q = 2 * l; q < N - 2 * l; ++q) {
+            const T um1 = shr1(u[q]), up1 = shl1(u[q]);
+            const T um2 = shr1(um1), up2 = shl1(up1);
+            const int j = jb + q;
+            if (col_in && j >= 0 && j < ny) u[q] = level1d(um2, um1, u[q], up1, up2, i, nx, p, cx);
         }
-        __syncthreads();
+        if (l == D - 1)
+            break;
+        // y-level on rows [2l+2, N-2l-2), from the old values of the column
+        T v[N];
 #pragma unroll
-        for (int q = 0; q < G::XPer; ++q) {
-            const int k = tid + q * kThreads;
-            if (k < w * hx) A[2 * l + k / w][2 * l + 2 + k % w] = xv[q];
+        for (int q = 2 * l + 2; q < N - 2 * l - 2; ++q) {
+            const int j = jb + q;
+            v[q] = (col_in && j >= 0 && j < ny)
+                       ? level1d(u[q - 2], u[q - 1], u[q], u[q + 1], u[q + 2], j, ny, p, cy)
+                       : u[q];
         }
-        __syncthreads();
-        if (l == D - 1) {
-            // the last y-level covers exactly the tile: straight to HBM
 #pragma unroll
-            for (int q = 0; q < G::YPer; ++q) {
-                const int k = tid + q * kThreads;
-                if (k < w * hy) {
-                    const int r = 2 * l + 2 + k / w, c = 2 * l + 2 + k % w;
-                    const int j = jb + r, i = ib + c;
-                    if (j < ny && i < nx)
-                        out[(int64_t)j * nx + i] = level1d(A[r - 2][c], A[r - 1][c], A[r][c],
-                                                           A[r + 1][c], A[r + 2][c], j, ny, p, cy);
-                }
-            }
-        } else {
-            T yv[G::YPer];
+        for (int q = 2 * l + 2; q < N - 2 * l - 2; ++q) u[q] = v[q];
+    }
+    // the last y-level: lanes H .. 63-H, rows H .. H+R-1, straight to HBM
+    if (lane < H || lane >= kWave - H || !col_in)
+        return;
+    const int p = (p0 + D - 1) & 1;
 #pragma unroll
-            for (int q = 0; q < G::YPer; ++q) {
-                const int k = tid + q * kThreads;
-                T y = T(0);
-                if (k < w * hy) {
-                    const int r = 2 * l + 2 + k / w, c = 2 * l + 2 + k % w;
-                    const int j = jb + r, i = ib + c;
-                    y = A[r][c];
-                    if (j >= 0 && j < ny && i >= 0 && i < nx)
-                        y = level1d(A[r - 2][c], A[r - 1][c], y, A[r + 1][c], A[r + 2][c], j, ny, p,
-                                    cy);
-                }
-                yv[q] = y;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < G::YPer; ++q) {
-                const int k = tid + q * kThreads;
-                if (k < w * hy) A[2 * l + 2 + k / w][2 * l + 2 + k % w] = yv[q];
-            }
-            __syncthreads();
-        }
+    for (int q = H; q < H + R; ++q) {
+        const int j = jb + q;
+        if (j < ny)
+            out[(int64_t)j * nx + i] = level1d(u[q - 2], u[q - 1], u[q], u[q + 1], u[q + 2], j, ny, p,
+                                               cy);
     }
 }
 
@@ -189,12 +155,16 @@ template <typename T> Line<T> line_coef(double r)
 }
 
 template <typename T, int D>
-hipError_t launch_levels(const T *src, T *dst, const Grid2dArgs &a, int64_t m, hipStream_t stream)
+hipError_t launch_reg_levels(const T *src, T *dst, const Grid2dArgs &a, int64_t m,
+                             hipStream_t stream)
 {
-    const int64_t tx = (a.nx + kTI - 1) / kTI, ty = (a.ny + Tile<T, D>::TJ - 1) / Tile<T, D>::TJ;
-    const int64_t ntiles = tx * ty, grid = (ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((level2d_kernel<T, D>), dim3((unsigned)grid), dim3(kThreads), 0, stream, src,
-                       dst, (int)a.nx, (int)a.ny, (int)tx, (int)ntiles, (int)(m & 1),
+    using G = RegTile<D>;
+    const int64_t strips = (a.nx + G::COLS - 1) / G::COLS, rows = (a.ny + G::R - 1) / G::R;
+    const int64_t ntiles = strips * rows;
+    const int64_t blocks = (ntiles + kThreads / kWave - 1) / (kThreads / kWave);
+    const int64_t grid = (blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL((level2d_reg_kernel<T, D>), dim3((unsigned)grid), dim3(kThreads), 0, stream,
+                       src, dst, (int)a.nx, (int)a.ny, (int)strips, (int)ntiles, (int)(m & 1),
                        line_coef<T>(a.rx), line_coef<T>(a.ry), (T)a.gw, (T)a.ge, (T)a.gs, (T)a.gn);
     return hipGetLastError();
 }
@@ -209,9 +179,9 @@ hipError_t launch_2d_t(const Grid2dArgs &a, hipStream_t stream)
         // D levels per launch while D remain, then single levels
         const int d = a.nsteps - s >= a.depth ? a.depth : 1;
         hipError_t e;
-        if (d == 4) e = launch_levels<T, 4>(src, dst, a, a.step0 + s, stream);
-        else if (d == 2) e = launch_levels<T, 2>(src, dst, a, a.step0 + s, stream);
-        else e = launch_levels<T, 1>(src, dst, a, a.step0 + s, stream);
+        if (d == 4) e = launch_reg_levels<T, 4>(src, dst, a, a.step0 + s, stream);
+        else if (d == 2) e = launch_reg_levels<T, 2>(src, dst, a, a.step0 + s, stream);
+        else e = launch_reg_levels<T, 1>(src, dst, a, a.step0 + s, stream);
         if (e != hipSuccess) return e;
         s += d;
         ++launches;
@@ -230,7 +200,7 @@ hipError_t launch_2d_t(const Grid2dArgs &a, hipStream_t stream)
 
 hipError_t launch_2d(int prec, const Grid2dArgs &a, hipStream_t stream)
 {
-    const int64_t tiles = ((a.nx + kTI - 1) / kTI) * ((a.ny + 15) / 16);
+    const int64_t tiles = ((a.nx + 47) / 48) * ((a.ny + 15) / 16);   // most tiles, D = 4
     // indices inside a launch are 32-bit: rows and columns below 2^31
     if (a.nx < 1 || a.ny < 1 || a.nx > 0x7fffff00LL || a.ny > 0x7fffff00LL || tiles > 0x7ffffff0LL ||
         (a.depth != 1 && a.depth != 2 && a.depth != 4))

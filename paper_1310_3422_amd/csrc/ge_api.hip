@@ -502,10 +502,10 @@ ge_status ge_comp_from_fp64(const double *x, float *pair, int64_t n, void *strea
 }
 
 // Levels per launch of the 2D extension when the caller leaves it to the
-// library: measured on MI355X (4096^2 points), two fused levels ran as fast
-// as one in FP64 and 15% slower in FP32, four 17-30% slower (the halo
-// recompute and two barriers per level outweigh the saved HBM traffic).
-constexpr int kDepth2d = 1;
+// library: measured on MI355X (4096^2 points), two levels per launch ran
+// 29% (FP64) and 17% (FP32) faster than one, four slower than two (the
+// recomputed halo grows faster than the saved HBM traffic).
+constexpr int kDepth2d = 2;
 
 size_t ge_2d_workspace_bytes(const ge_2d_desc *d)
 {

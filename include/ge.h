@@ -28,6 +28,13 @@
  *    has been enqueued (GE_ERR_HIP excepted: a launch error may follow work
  *    already enqueued by the same call).  ge_last_error() gives a message for
  *    the last failing call of the calling thread.
+ *  - Device-side conditions (a NaN or infinite value stored by a launch, a
+ *    wait between waves that gave up) are recorded in status words of the
+ *    plan (pinned, host-mapped memory the kernels write).  The next call on
+ *    the plan reports a condition raised by a launch that has finished by
+ *    then (GE_ERR_NONFINITE, GE_ERR_SYNC; nothing is enqueued by that call,
+ *    and the word is cleared); ge_plan_check / ge_batch_check wait for the
+ *    stream first, so they report every launch enqueued before them.
  *  - Results are bit-for-bit reproducible: they do not depend on the tiling,
  *    the number of levels fused per launch, the grid, or how a run is split
  *    into calls.
@@ -48,7 +55,9 @@ typedef enum {
     GE_ERR_NOMEM = 2,        /* a host or plan-time device allocation failed */
     GE_ERR_HIP = 3,          /* the HIP runtime reported an error            */
     GE_ERR_UNSUPPORTED = 4,  /* valid request this build does not handle     */
-    GE_ERR_NONFINITE = 5     /* a parameter or value is NaN or infinite      */
+    GE_ERR_NONFINITE = 5,    /* a parameter or value is NaN or infinite      */
+    GE_ERR_SYNC = 6          /* a wait between waves inside a launch gave up */
+                             /* (the results of that launch are not valid)   */
 } ge_status;
 
 typedef enum {
@@ -77,7 +86,8 @@ int64_t ge_comp_offset(int64_t n);
  * A plan fixes the problem of Section 2 for one rod: n, r, the precision,
  * the default (constant) wall values and, optionally, a source
  * f(x, t) = a(t) b(x) whose profile b(x_i) is given here and whose time
- * factor a is given per call.  A plan holds host-side metadata only.
+ * factor a is given per call.  A plan holds host-side metadata and its
+ * status words (pinned host memory).
  * ---------------------------------------------------------------------- */
 typedef struct ge_plan_s *ge_plan_t;
 
@@ -129,8 +139,16 @@ size_t ge_workspace_bytes(const ge_desc *desc);
  * GE_ERR_NONFINITE (r, g_left or g_right not finite), GE_ERR_NOMEM. */
 ge_status ge_plan(ge_plan_t *out, const ge_desc *desc);
 
-/* Release a plan (NULL is ignored).  Work already enqueued is unaffected. */
+/* Release a plan (NULL is ignored).  Work already enqueued is unaffected
+ * (a plan that has launched work waits for the device first: its kernels
+ * hold the plan's status words). */
 void ge_destroy(ge_plan_t plan);
+
+/* Wait for `stream`, then report what the plan's launches raised since the
+ * last report: GE_ERR_NONFINITE if one of them stored a NaN or infinite
+ * value in the state (every stored value is tested), else GE_OK.  The word
+ * is cleared.  Errors: GE_ERR_INVALID (NULL plan), GE_ERR_HIP. */
+ge_status ge_plan_check(ge_plan_t plan, void *stream);
 
 /* Advance the state `u` (device, layout above) from global level `step0` to
  * level step0 + nsteps.  The parity of each level, hence its grouping, is
@@ -149,7 +167,9 @@ void ge_destroy(ge_plan_t plan);
  * u and workspace must be 16-byte aligned.  nsteps = 0 enqueues nothing.
  * Errors: GE_ERR_INVALID (null plan/u/workspace, negative step0 or nsteps,
  * misalignment, aliasing, source array missing or unexpected),
- * GE_ERR_UNSUPPORTED (flux with a sub-domain plan), GE_ERR_HIP. */
+ * GE_ERR_UNSUPPORTED (flux with a sub-domain plan), GE_ERR_NONFINITE (an
+ * earlier launch of this plan, finished by now, stored a NaN or infinite
+ * value; nothing is enqueued), GE_ERR_HIP. */
 ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0,
                     int64_t nsteps, const double *g_left_t,
                     const double *g_right_t, const double *src_a_t,
@@ -222,9 +242,13 @@ ge_status ge_2d_step_n(const ge_2d_desc *desc, void *u, void *workspace, int64_t
  * the buffer length in elements.  Every offsets[i] must be a multiple of 4 and
  * offsets[i+1] >= offsets[i] + n[i].
  *
- * Each rod is held in registers of one workgroup for all levels, which caps
- * n at 65536 (GE_FP32) or 32768 (GE_FP64, GE_FP32_COMP); longer rods go
- * through ge_step_n.
+ * A rod of up to 65536 (GE_FP32) or 32768 (GE_FP64, GE_FP32_COMP) points is
+ * held in registers of one workgroup for all levels, so it is read and
+ * written once per call.  A longer rod takes a workgroup of its own and is
+ * swept the way ge_step_n sweeps a rod: in passes of up to 32 levels over
+ * windows with recomputed halos, ping-ponging between u and its own second
+ * level buffer in the workspace (an even number of passes, so the result
+ * lands in u).  Every rod gets the same bits as ge_step_n gives it.
  * ---------------------------------------------------------------------- */
 typedef struct ge_batch_s *ge_batch_t;
 
@@ -257,8 +281,7 @@ typedef struct {
  * tables to device memory owned by the plan (freed by ge_batch_destroy).
  * With tune = 1 this runs timing kernels on the current device.  Every
  * choice gives bit-identical results.  Errors: GE_ERR_INVALID,
- * GE_ERR_NONFINITE, GE_ERR_UNSUPPORTED (a rod above the on-chip limit),
- * GE_ERR_NOMEM, GE_ERR_HIP. */
+ * GE_ERR_NONFINITE, GE_ERR_NOMEM, GE_ERR_HIP. */
 ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *desc);
 
 /* Release a batch plan and its graph (NULL is ignored). */
@@ -267,8 +290,29 @@ void ge_batch_destroy(ge_batch_t batch);
 /* Elements of the packed state buffer (see the layout above); -1 for NULL. */
 int64_t ge_batch_state_elems(ge_batch_t batch);
 
-/* Bytes of device workspace ge_solve_batch needs (the task queue head). */
+/* Bytes of device workspace ge_solve_batch needs: 256 (the task queue head),
+ * plus, when rods are above the on-chip limit, their second level buffers
+ * from byte 256 on (each rod's points rounded up to 64 elements, twice for
+ * GE_FP32_COMP). */
 size_t ge_batch_workspace_bytes(ge_batch_t batch);
+
+/* Number of polls (each a short sleep, about 30 ns) a wave's wait for a
+ * neighbouring wave makes before it gives up (default 65536).  The waits
+ * belong to rods whose waves exchange edge values every level (sync = 2, or
+ * the rods sync = 3 cannot give overlapping lanes); they always end within
+ * microseconds, and the bound only keeps a wave from spinning forever.  A
+ * wait that gives up raises GE_ERR_SYNC for the next ge_solve_batch or
+ * ge_batch_check.  polls = 0 makes every wait give up without looking (a
+ * test of that path; every kernel still exits normally).  Drops the
+ * plan's captured graphs.  Errors: GE_ERR_INVALID (NULL, polls < 0 or above
+ * 2^30). */
+ge_status ge_batch_set_wait_polls(ge_batch_t batch, int64_t polls);
+
+/* Wait for `stream`, then report what the plan's runs raised since the last
+ * report: GE_ERR_SYNC (a wait gave up), else GE_ERR_NONFINITE (a stored
+ * value was NaN or infinite), else GE_OK.  The reported word is cleared.
+ * Errors: GE_ERR_INVALID (NULL batch), GE_ERR_HIP. */
+ge_status ge_batch_check(ge_batch_t batch, void *stream);
 
 /* The plan's shape: number of tasks, resident workgroups, the planner's
  * estimate of the time of one level in microseconds, and (if rod_k is not
@@ -282,7 +326,8 @@ ge_status ge_batch_info(ge_batch_t batch, int32_t *ntasks, int32_t *grid,
  * by another run at the same time.  The first call for a given (u,
  * workspace, parity of step0, nsteps) captures the queue reset and the
  * persistent launch in a hipGraph; later calls with the same key replay it
- * on `stream`.  Errors: GE_ERR_INVALID, GE_ERR_HIP. */
+ * on `stream`.  Errors: GE_ERR_INVALID, GE_ERR_SYNC or GE_ERR_NONFINITE (an
+ * earlier run, finished by now, raised it; nothing is enqueued), GE_ERR_HIP. */
 ge_status ge_solve_batch(ge_batch_t batch, void *u, void *workspace,
                          int64_t step0, int64_t nsteps, void *stream);
 
@@ -367,6 +412,33 @@ ge_status ge_nn_advance(ge_nn_t net, ge_batch_t ge, void *ge_ws, float *u, const
                         int32_t batch, int64_t step0, int32_t njumps, int32_t check,
                         double tol, int32_t *accepted, int32_t *fallbacks, double *last_err,
                         int64_t *n_fallback, void *stream);
+
+/* Shape of layer `layer` (1..6): real input and output channels (ci, co),
+ * the padded channels its activations are stored with on the device (input
+ * cip, output cop), the padded channels of the gradient entering it from
+ * its output (cod), and its tap spacing (dil).  Any pointer may be NULL.
+ * Errors: GE_ERR_INVALID (layer outside 1..6). */
+ge_status ge_nn_layer_shape(int32_t layer, int32_t *ci, int32_t *co, int32_t *cip, int32_t *cop,
+                            int32_t *cod, int32_t *dil);
+
+/* One product of one layer on caller-given bfloat16 operands, with the
+ * network's current (bfloat16-packed) weights, each result in FP32 before
+ * any rounding -- a probe for tests that check the matrix-core products
+ * against an oracle fed the same operands.  Arrays are device memory,
+ * channels last, `batch` rods of the network's width:
+ *   op 0, forward:        x: bf16 [batch][width][cip]; out: float
+ *                         [batch][width][cop] = conv(x, W) + b;
+ *   op 1, input gradient: g: bf16 [batch][width][cod]; out: float
+ *                         [batch][width][cip], the gradient of
+ *                         sum(conv(x, W) g) with respect to x (layers 2..6);
+ *   op 2, weight gradient: x as op 0, g as op 1; out: float, the flat
+ *                         gradient of the layer, dW[5][co][ci] then db[co]
+ *                         (the order of ge_nn_param_count's layout).
+ * Padded channels of x and g must hold zeros.  Uses the network's scratch
+ * buffers: do not overlap with other calls on the same network.  Errors:
+ * GE_ERR_INVALID (network, layer, op, batch or a NULL array), GE_ERR_HIP. */
+ge_status ge_nn_layer_probe(ge_nn_t net, int32_t layer, int32_t op, const void *x, const void *g,
+                            int32_t batch, float *out, void *stream);
 
 /* Element-wise precision conversions on the device (n elements, enqueued on
  * the stream): FP32 to FP64 and FP64 to FP32 (round to nearest). */

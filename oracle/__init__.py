@@ -73,9 +73,11 @@ def grid(n):
 
 
 def step_n(u0, r, nsteps, step0=0, gl=0.0, gr=0.0, src_b=None, src_a=None,
-           tau=None, h=None, flux=None, nthreads=1, extended=False):
+           tau=None, h=None, flux=None, nthreads=1, extended=False, inplace=False):
     """Advance interior values ``u0`` (u_1..u_n at level ``step0``) by
-    ``nsteps`` levels and return the new array (``u0`` is not modified).
+    ``nsteps`` levels and return the new array (``u0`` is not modified,
+    unless ``inplace``: then ``u0``, a contiguous float64 array, is advanced
+    in place and returned).
 
     gl, gr: wall values, either scalars (constant) or arrays of length
     nsteps+1 holding g(t_m) for m = step0..step0+nsteps.
@@ -87,7 +89,13 @@ def step_n(u0, r, nsteps, step0=0, gl=0.0, gr=0.0, src_b=None, src_a=None,
     first-difference sums (see ge_ref_core.inc).
     """
     lib = _load()
-    u = np.array(u0, dtype=np.float64, copy=True).ravel()
+    if inplace:
+        if not (isinstance(u0, np.ndarray) and u0.dtype == np.float64 and u0.ndim == 1
+                and u0.flags.c_contiguous and u0.flags.writeable):
+            raise ValueError("inplace needs a writeable contiguous 1-D float64 array")
+        u = u0
+    else:
+        u = np.array(u0, dtype=np.float64, copy=True).ravel()
     n = u.size
     if h is None:
         h = 1.0 / (n + 1)

@@ -41,6 +41,44 @@ ge_status set_error(ge_status st, const char *fmt, ...)
 
 const char *last_error_str() { return g_last_error.c_str(); }
 
+bool status_alloc(StatusWords &w)
+{
+    w = StatusWords{};
+    void *h = nullptr;
+    if (hipHostMalloc(&h, kStatusWords * sizeof(int),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess || !h) {
+        (void)hipGetLastError();
+        return false;
+    }
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || !d) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h);
+        return false;
+    }
+    w.host = static_cast<int *>(h);
+    w.dev = static_cast<int *>(d);
+    for (int i = 0; i < kStatusWords; ++i) w.host[i] = 0;
+    return true;
+}
+
+void status_free(StatusWords &w)
+{
+    if (!w.host) return;
+    (void)hipDeviceSynchronize();
+    (void)hipHostFree(w.host);
+    w = StatusWords{};
+}
+
+bool status_take(StatusWords &w, int word)
+{
+    if (!w.host) return false;
+    volatile int *h = w.host;
+    if (h[word] == 0) return false;
+    h[word] = 0;
+    return true;
+}
+
 SchemeCoef scheme_coef(double r)
 {
     SchemeCoef c;
@@ -135,6 +173,8 @@ struct ge_plan_s {
     double g_left, g_right;
     const void *src_b;
     double c1, c2, cs, e1, e2, es, tau, h;
+    ge::StatusWords status;   // word 0: a launch stored a NaN or infinite value
+    bool launched;            // a kernel may hold the status pointer
 };
 
 namespace {
@@ -220,6 +260,7 @@ ge_status plan_sdc(ge_plan_t *out, const ge_desc *d)
     p->cs = sc.cs;
     p->e1 = (1.0 - r) / (1.0 + r);       // the sweep's own-value weight
     p->e2 = p->es = 0.0;
+    (void)ge::status_alloc(p->status);
     *out = p;
     return GE_OK;
 }
@@ -241,6 +282,7 @@ const char *ge_status_str(int status)
     case GE_ERR_HIP: return "GE_ERR_HIP";
     case GE_ERR_UNSUPPORTED: return "GE_ERR_UNSUPPORTED";
     case GE_ERR_NONFINITE: return "GE_ERR_NONFINITE";
+    case GE_ERR_SYNC: return "GE_ERR_SYNC";
     default: return "GE_ERR_UNKNOWN";
     }
 }
@@ -353,11 +395,30 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
     p->e1 = p->tau * (1.0 + r) / (1.0 + 2.0 * r);
     p->e2 = p->tau * r / (1.0 + 2.0 * r);
     p->es = p->tau / (1.0 + r);
+    (void)ge::status_alloc(p->status);
     *out = p;
     return GE_OK;
 }
 
-void ge_destroy(ge_plan_t plan) { delete plan; }
+void ge_destroy(ge_plan_t plan)
+{
+    if (!plan) return;
+    if (plan->launched) ge::status_free(plan->status);
+    else if (plan->status.host) (void)hipHostFree(plan->status.host);
+    delete plan;
+}
+
+ge_status ge_plan_check(ge_plan_t plan, void *stream)
+{
+    if (!plan)
+        return fail(GE_ERR_INVALID, "ge_plan_check: plan is NULL");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "ge_plan_check: stream synchronize");
+    if (ge::status_take(plan->status, ge::kStatusNonfinite))
+        return fail(GE_ERR_NONFINITE, "ge_plan_check: a launch stored a NaN or infinite value");
+    return GE_OK;
+}
 
 ge_status ge_plan_config(ge_plan_t plan, int32_t *tile, int32_t *depth, int32_t *waves,
                          int32_t *halo)
@@ -405,8 +466,12 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
     }
     if (plan->sdc && flux)
         return fail(GE_ERR_UNSUPPORTED, "ge_step_n: the sub-domain scheme keeps no wall flux");
+    if (ge::status_take(plan->status, ge::kStatusNonfinite))
+        return fail(GE_ERR_NONFINITE,
+                    "ge_step_n: an earlier launch of this plan stored a NaN or infinite value");
     if (nsteps == 0)
         return GE_OK;
+    plan->launched = true;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     ge::TileArgs a{};
@@ -417,10 +482,12 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
     a.ntiles = plan->ntiles;
     a.halo = plan->halo;
     a.estride = plan->prec == ge::kFP32C ? ge::comp_offset(plan->n) : 0;
+    a.estride_out = a.estride;
     a.c1 = plan->c1; a.c2 = plan->c2; a.cs = plan->cs;
     a.e1 = plan->e1; a.e2 = plan->e2; a.es = plan->es;
     a.gl0 = plan->g_left; a.gr0 = plan->g_right;
     a.tau = plan->tau; a.h = plan->h;
+    a.status = plan->status.dev;
     const bool src = plan->src_b != nullptr;
     if (plan->sdc) {
         a.nsdc = (plan->n + 1) / plan->tile;

@@ -14,13 +14,18 @@ struct BatchRod {
     int64_t n;                // interior points
     double c1, c2, cs;        // (r+r^2)/(1+2r), r^2/(1+2r), r/(1+r)
     double gl, gr;            // constant wall values
+    int64_t woff;             // rod above the on-chip limit: element offset of
+                              // its second level buffer in u2; else -1
 };
 
 // One unit of work for a workgroup: rods sharing points-per-lane k, each
 // owning a contiguous range of the workgroup's waves (-1: wave idle).
 // halo = 1: the rods' waves overlap by one lane on each side and exchange
 // those lanes every k-1 levels; halo = 0: adjacent waves exchange their edge
-// values every level.
+// values every level; halo = 2: one rod too long for the workgroup's
+// registers (wave_rod[0]), swept in passes of at most BatchArgs::long_depth
+// levels over single-wave windows of 64k points with halos, ping-ponging
+// between u and the workspace's second level buffer.
 struct BatchTask {
     int32_t k;
     int32_t halo;
@@ -39,8 +44,17 @@ struct BatchArgs {
     int32_t ntasks;
     int32_t sync;             // 1: workgroup barrier per level; 2: neighbour flags;
                               // 3: halo lanes (tasks with halo = 0 use flags)
-    int32_t pad;
+    int32_t wait_polls;       // polls before a neighbour wait gives up
+    int *status;              // host-mapped status words (StatusWord), or null
+    void *u2;                 // second level buffers of the long rods (s block,
+                              // then the e block at estride2 for FP32C)
+    int64_t estride2;
+    int32_t long_depth;       // levels per pass of a long-rod task
+    int32_t long_halo;        // window points each side of its cores
 };
+
+// Points per lane of the single-wave windows of long-rod tasks.
+constexpr int batch_long_k(int prec) { return prec == 1 ? 32 : 16; }
 
 // Waves a rod of n points needs at k points per lane when neighbouring
 // waves overlap by one lane (halo tasks): 64k points for the first wave and
@@ -81,6 +95,7 @@ struct HaloLayout {
 };
 
 hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream);
+
 int batch_max_k(int prec);
 
 }  // namespace ge

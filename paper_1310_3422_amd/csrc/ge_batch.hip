@@ -26,6 +26,7 @@
 #include "ge_batch.h"
 #include "ge_kernels.h"
 #include "ge_level.h"
+#include "ge_tile.h"
 
 namespace ge {
 namespace {
@@ -37,15 +38,22 @@ constexpr int kThreads = kWaves * kWave;
 
 // Wait until a neighbouring wave has published the edges of the level this
 // wave is on.  Every wave publishes before it waits, so a wait on level i
-// ends once the neighbour has finished level i - 1 (a few microseconds); the
-// bound of 65536 polls (milliseconds) only keeps a wave from spinning forever
-// should that ever fail.
-__device__ __forceinline__ void wait_level(const int *flag, int tag)
+// ends once the neighbour has finished level i - 1 (a few microseconds).
+// The bound on the polls (BatchArgs::wait_polls, by default 65536, about
+// two milliseconds) only keeps a wave from spinning forever should that ever
+// fail; a wait that gives up raises kStatusWaitGaveUp, which the next call
+// on the plan reports, since the wave then goes on with edge values that
+// may be stale.
+__device__ __forceinline__ void wait_level(const int *flag, int tag, int polls, int *status)
 {
-    int n = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < tag) {
+    for (int n = 0;; ++n) {
+        if (n >= polls) {
+            if (status && (threadIdx.x & (kWave - 1)) == 0) raise_status(status, kStatusWaitGaveUp);
+            break;
+        }
+        if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= tag)
+            break;
         __builtin_amdgcn_s_sleep(1);
-        if (++n > (1 << 16)) break;
     }
 }
 
@@ -99,8 +107,8 @@ __device__ __forceinline__ void rod_levels(const BatchArgs &a, const BatchRod &r
             const int tag = lev + 1;   // lev counts this call's levels from 0
             if (lane == 0)
                 __hip_atomic_store(&lvl[w], tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (wr > 0) wait_level(&lvl[w - 1], tag);
-            if (hasR) wait_level(&lvl[w + 1], tag);
+            if (wr > 0) wait_level(&lvl[w - 1], tag, a.wait_polls, a.status);
+            if (hasR) wait_level(&lvl[w + 1], tag, a.wait_polls, a.status);
         } else {
             __syncthreads();
         }
@@ -181,6 +189,7 @@ __device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk
             rod_levels<T, K, COMP, false, NBR>(a, rd, wr, hasR, s, e, xs, xe, lvl);
     }
     if (rod >= 0) {
+        check_finite<T, K, COMP>(a.status, s, e, g0, 0, rd.n);
         store_lane_upto<T, K>(us + g0, g0, rd.n, s);
         if constexpr (COMP) store_lane_upto<T, K>(ue + g0, g0, rd.n, e);
     }
@@ -461,11 +470,73 @@ __device__ __forceinline__ void run_task_halo(const BatchArgs &a, const BatchTas
     }
     // lanes 1..62, lane 0 of the first wave and lane 63 of the last (the last
     // wave from its neighbour's core end on)
+    if (rod >= 0) {
+        const bool mine = (lane > 0 || wr == 0) && (lane < kWave - 1 || !hasR);
+        check_finite<T, K, COMP>(a.status, s, e, g0, mine ? lo : rd.n, rd.n);
+    }
     if (rod >= 0 && (lane > 0 || wr == 0) && (lane < kWave - 1 || !hasR)) {
         store_lane_range<T, K>(us + g0, g0, lo, rd.n, s);
         if constexpr (COMP) store_lane_range<T, K>(ue + g0, g0, lo, rd.n, e);
     }
     __syncthreads();   // LDS slots are reused by the next task
+}
+
+// ---- long-rod tasks ------------------------------------------------------
+// A rod longer than the workgroup's registers hold is swept the way a single
+// rod is (ge_tile.h): windows of 64 K points, one per wave, advance up to
+// long_depth levels in registers with open edges and store their cores, the
+// halo of long_halo >= levels + 1 points per side absorbing what enters from
+// the open edges.  The 16 waves take the windows of a pass round-robin, and a
+// workgroup barrier separates the passes; no other workgroup touches the
+// rod, so no wait crosses workgroups.  The passes ping-pong between u and the
+// rod's own second level buffer in u2 and their number is even, so the
+// result lands in u.  Every point gets the same operations as in every other
+// path, so the bits equal those of ge_step_n.
+template <typename T, int K, bool COMP>
+__device__ __forceinline__ void run_task_long(const BatchArgs &a, const BatchTask &tk)
+{
+    constexpr int64_t W = (int64_t)kWave * K;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const BatchRod rd = a.rods[tk.wave_rod[0]];
+    TileArgs ta{};
+    ta.n = rd.n;
+    ta.halo = a.long_halo;
+    ta.core = W - 2 * (int64_t)a.long_halo;
+    ta.ntiles = (rd.n + ta.core - 1) / ta.core;
+    ta.c1 = rd.c1;
+    ta.c2 = rd.c2;
+    ta.cs = rd.cs;
+    ta.gl0 = rd.gl;
+    ta.gr0 = rd.gr;
+    ta.h = 1.0;
+    ta.status = a.status;
+    T *b0 = static_cast<T *>(a.u) + rd.off;
+    T *b1 = static_cast<T *>(a.u2) + rd.woff;
+    int64_t passes = (a.nsteps + a.long_depth - 1) / a.long_depth;
+    passes += passes & 1;
+    const int64_t base = a.nsteps / passes, extra = a.nsteps % passes;
+    int64_t done = 0;
+    for (int64_t ps = 0; ps < passes; ++ps) {
+        const int lev = (int)(base + (ps < extra ? 1 : 0));
+        ta.in = (ps & 1) ? b1 : b0;
+        ta.out = (ps & 1) ? b0 : b1;
+        ta.estride = (ps & 1) ? a.estride2 : a.estride;
+        ta.estride_out = (ps & 1) ? a.estride : a.estride2;
+        ta.level0 = a.step0 + done;
+        ta.nlev = lev;
+        for (int64_t t = w; t < ta.ntiles; t += kWaves) {
+            const int64_t ws = t == 0 ? 0 : t * ta.core - ta.halo;
+            if (ws == 0 || ws + W >= rd.n)
+                run_tile<T, K, 1, COMP, false, true>(ta, lane, t, ws);
+            else
+                run_tile<T, K, 1, COMP, false, false>(ta, lane, t, ws);
+        }
+        // the next pass reads what every wave stored (same workgroup: the
+        // barrier orders the global stores before the loads)
+        __syncthreads();
+        done += lev;
+    }
 }
 
 // SYNC: 1 = barrier per level, 2 = neighbour flags, 3 = halo lanes (tasks
@@ -486,6 +557,11 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
         if (task >= a.ntasks)
             break;
         const BatchTask &tk = a.tasks[task];
+        if (tk.halo == 2) {
+            run_task_long<T, batch_long_k(sizeof(T) == 8 ? kFP64 : (COMP ? kFP32C : kFP32)), COMP>(
+                a, tk);
+            continue;
+        }
         if (SYNC == 3 && tk.halo) {
             switch (tk.k) {
             case 4: run_task_halo<T, 4, COMP>(a, tk, hx, he); break;
@@ -515,6 +591,7 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
 __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
 
 }  // namespace
+
 
 hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream)
 {

@@ -146,11 +146,40 @@ int rod_waves(int64_t n, int k, bool halo_mode, int *halo)
     return waves_for(n, k);
 }
 
+// Polls a neighbour wait makes before it gives up (about two milliseconds).
+constexpr int kDefaultWaitPolls = 1 << 16;
+
 struct Plan {
     std::vector<int> rod_k;
     std::vector<BatchTask> tasks;
     double est_us = 0;
+    bool has_long = false;
 };
+
+// Levels per pass of a long-rod task, and its halo (levels + 1, rounded up
+// to the 16-byte chunk of the state type).
+constexpr int kLongDepth = 32;
+int long_halo(int prec)
+{
+    const int align = prec == ge::kFP64 ? 2 : 4;
+    return (kLongDepth + 1 + align - 1) / align * align;
+}
+
+// Points the registers of one workgroup hold (the on-chip limit); longer
+// rods run as long-rod tasks.
+int64_t on_chip_cap(int prec) { return (int64_t)kBatchWaves * 64 * ge::batch_max_k(prec); }
+
+// Per-level cost of a long-rod task: its 16 waves take the rod's windows in
+// rounds, each round about one level of a 16-wave task at the same points
+// per lane, plus the pass's trip through memory.
+double long_cost(int64_t n, int prec, const CostModel &cm)
+{
+    const int k = ge::batch_long_k(prec);
+    const int64_t core = 64 * (int64_t)k - 2 * long_halo(prec);
+    const int64_t wins = (n + core - 1) / core;
+    const int64_t rounds = (wins + kBatchWaves - 1) / kBatchWaves;
+    return (double)rounds * cm.k[k_index(k)].base * 1.15;
+}
 
 // Bundle rods into workgroup tasks.  Rods are placed largest first; each rod
 // goes into an open task of some feasible K where it fits (those waves are
@@ -168,14 +197,23 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
 
     Plan P;
     P.rod_k.assign(nr, 0);
-    struct Bin { int k; int halo; int used; int nwall; };
+    struct Bin { int k; int halo; int used; int nwall; double cost; };
     std::vector<Bin> bins;
     std::vector<std::vector<int>> members;
     auto task_cost = [&](int k, int nwall) {
         const KCost &c = cm.k[k_index(k)];
         return c.base + c.wall * (double)nwall / kBatchWaves;
     };
+    const int64_t cap = on_chip_cap(prec);
     for (int r : order) {
+        if (n[r] > cap) {
+            // a task of its own, swept in passes
+            bins.push_back(Bin{ge::batch_long_k(prec), 2, kBatchWaves, 2, long_cost(n[r], prec, cm)});
+            members.push_back({r});
+            P.rod_k[r] = ge::batch_long_k(prec);
+            P.has_long = true;
+            continue;
+        }
         int best_bin = -1, best_left = 1 << 30;
         int best_k = 0, best_h = 0;
         double best_new = 1e300;
@@ -201,7 +239,7 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
             }
         }
         if (best_bin < 0) {
-            bins.push_back(Bin{best_k, best_h, 0, 0});
+            bins.push_back(Bin{best_k, best_h, 0, 0, 0.0});
             members.emplace_back();
             best_bin = (int)bins.size() - 1;
         }
@@ -213,12 +251,13 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
         members[best_bin].push_back(r);
         P.rod_k[r] = b.k;
     }
+    for (Bin &b : bins)
+        if (b.halo != 2) b.cost = task_cost(b.k, b.nwall);
     // largest first
     std::vector<int> border(bins.size());
     for (size_t i = 0; i < bins.size(); ++i) border[i] = (int)i;
-    std::stable_sort(border.begin(), border.end(), [&](int a, int b) {
-        return task_cost(bins[a].k, bins[a].nwall) > task_cost(bins[b].k, bins[b].nwall);
-    });
+    std::stable_sort(border.begin(), border.end(),
+                     [&](int a, int b) { return bins[a].cost > bins[b].cost; });
     std::vector<double> load(std::max(grid, 1), 0.0);
     for (int bi : border) {
         BatchTask t;
@@ -228,7 +267,7 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
         int w = 0;
         for (int r : members[bi]) {
             int hb = 0;
-            const int nw = rod_waves(n[r], t.k, halo_mode, &hb);
+            const int nw = t.halo == 2 ? 1 : rod_waves(n[r], t.k, halo_mode, &hb);
             for (int j = 0; j < nw; ++j) {
                 t.wave_rod[w] = r;
                 t.wave_idx[w] = j;
@@ -242,7 +281,7 @@ Plan make_plan(const std::vector<int64_t> &n, int prec, const CostModel &cm, int
         P.tasks.push_back(t);
         // earliest-free workgroup takes the next task
         auto it = std::min_element(load.begin(), load.end());
-        *it += task_cost(bins[bi].k, bins[bi].nwall) * (double)nsteps;
+        *it += bins[bi].cost * (double)nsteps;
     }
     P.est_us = load.empty() ? 0 : *std::max_element(load.begin(), load.end());
     return P;
@@ -272,6 +311,11 @@ struct ge_batch_s {
     int ntasks;
     int grid;
     double est_us;
+    bool has_long;          // some rod runs as a long-rod task (workspace holds u2)
+    int64_t long_elems;     // elements of one block of u2 (s; the pair has two)
+    int64_t estride2;       // element offset of u2's e block (FP32C)
+    int wait_polls;         // bound on a neighbour wait's polls
+    ge::StatusWords status; // words raised by the kernels
     BatchRod *d_rods;
     BatchTask *d_tasks;
     hipStream_t cap;        // private stream used only for capture
@@ -307,10 +351,30 @@ ge_status hip_fail(hipError_t e, const char *what)
     return ge::set_error(GE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Report (and clear) what finished launches of the plan raised.
+ge_status take_status(ge_batch_s *b, const char *who)
+{
+    if (ge::status_take(b->status, ge::kStatusWaitGaveUp))
+        return fail(GE_ERR_SYNC, "%s: a wave's wait for its neighbour gave up; the results of "
+                                 "that run are not valid", who);
+    if (ge::status_take(b->status, ge::kStatusNonfinite))
+        return fail(GE_ERR_NONFINITE, "%s: a run stored a NaN or infinite value", who);
+    return GE_OK;
+}
+
+// Drop the instantiated graphs (their kernel arguments are out of date).
+void drop_graphs(ge_batch_s *b)
+{
+    if (b->ngraphs > 0) (void)hipDeviceSynchronize();
+    for (int i = 0; i < b->ngraphs; ++i) (void)hipGraphExecDestroy(b->graphs[i].exec);
+    b->ngraphs = 0;
+}
+
 void free_batch(ge_batch_s *b)
 {
     if (!b) return;
-    for (int i = 0; i < b->ngraphs; ++i) (void)hipGraphExecDestroy(b->graphs[i].exec);
+    drop_graphs(b);
+    ge::status_free(b->status);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->d_rods) (void)hipFree(b->d_rods);
     if (b->d_tasks) (void)hipFree(b->d_tasks);
@@ -337,7 +401,7 @@ double time_tasks(int prec, int sync, int k, bool walls, int grid, void *u, size
     if ((size_t)(stride * rods.size() * esz * (prec == ge::kFP32C ? 2 : 1)) > ubytes) return -1;
     const ge::SchemeCoef sc = ge::scheme_coef(2.0);
     for (size_t i = 0; i < rods.size(); ++i)
-        rods[i] = BatchRod{(int64_t)i * stride, rod_n, sc.c1, sc.c2, sc.cs, 0.25, -0.5};
+        rods[i] = BatchRod{(int64_t)i * stride, rod_n, sc.c1, sc.c2, sc.cs, 0.25, -0.5, -1};
     for (int t = 0; t < ntasks; ++t) {
         memset(&tasks[t], 0, sizeof(BatchTask));
         tasks[t].k = k;
@@ -362,6 +426,7 @@ double time_tasks(int prec, int sync, int k, bool walls, int grid, void *u, size
     a.nsteps = nsteps;
     a.ntasks = ntasks;
     a.sync = sync;
+    a.wait_polls = kDefaultWaitPolls;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -460,15 +525,10 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
     // library choice, measured on the 4096-rod batch: halo lanes (+23% FP32,
     // +21% pair, +26% FP64 over neighbour flags)
     const int sync = d->sync != 0 ? d->sync : 3;
-    const int64_t cap = (int64_t)kBatchWaves * 64 * ge::batch_max_k(prec);
     for (int64_t i = 0; i < d->nrods; ++i) {
         if (d->n[i] < 1)
             return fail(GE_ERR_INVALID, "ge_batch_plan: rod %lld has n = %lld", (long long)i,
                         (long long)d->n[i]);
-        if (d->n[i] > cap)
-            return fail(GE_ERR_UNSUPPORTED,
-                        "ge_batch_plan: rod %lld has n = %lld, above the on-chip limit %lld "
-                        "for this precision", (long long)i, (long long)d->n[i], (long long)cap);
         if (d->offsets[i] < 0 || d->offsets[i] % 4 != 0)
             return fail(GE_ERR_INVALID, "ge_batch_plan: offsets[%lld] must be >= 0 and a multiple of 4",
                         (long long)i);
@@ -514,15 +574,25 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
     b->n.assign(d->n, d->n + d->nrods);
     b->grid = device_grid();
 
+    // rods above the on-chip limit get their second level buffers back to
+    // back in u2, each starting on a 256-byte boundary
     std::vector<BatchRod> rods(d->nrods);
+    int64_t woff = 0;
     for (int64_t i = 0; i < d->nrods; ++i) {
         const ge::SchemeCoef sc = ge::scheme_coef(d->r[i]);
-        rods[i] = BatchRod{d->offsets[i], d->n[i], sc.c1, sc.c2, sc.cs, d->g_left[i], d->g_right[i]};
+        const bool lng = d->n[i] > on_chip_cap(prec);
+        rods[i] = BatchRod{d->offsets[i], d->n[i], sc.c1, sc.c2, sc.cs, d->g_left[i],
+                           d->g_right[i], lng ? woff : -1};
+        if (lng) woff += (d->n[i] + 63) / 64 * 64;
     }
+    b->long_elems = woff;
+    b->estride2 = prec == ge::kFP32C ? woff : 0;
     Plan P = make_plan(b->n, prec, cm, 1, b->grid, sync == 3);
     b->rod_k = P.rod_k;
     b->ntasks = (int)P.tasks.size();
     b->est_us = P.est_us;
+    b->has_long = P.has_long;
+    b->wait_polls = kDefaultWaitPolls;
     hipError_t e;
     if ((e = hipMalloc((void **)&b->d_rods, sizeof(BatchRod) * rods.size())) != hipSuccess ||
         (e = hipMalloc((void **)&b->d_tasks, sizeof(BatchTask) * P.tasks.size())) != hipSuccess) {
@@ -537,13 +607,48 @@ ge_status ge_batch_plan(ge_batch_t *out, const ge_batch_desc *d)
         free_batch(b);
         return hip_fail(e, "ge_batch_plan: setup");
     }
+    if (!ge::status_alloc(b->status)) {
+        free_batch(b);
+        return fail(GE_ERR_NOMEM, "ge_batch_plan: status words could not be allocated");
+    }
     *out = b;
     return GE_OK;
 }
 
 void ge_batch_destroy(ge_batch_t b) { free_batch(b); }
 
-size_t ge_batch_workspace_bytes(ge_batch_t b) { return b ? 256 : 0; }
+size_t ge_batch_workspace_bytes(ge_batch_t b)
+{
+    if (!b) return 0;
+    if (!b->has_long) return 256;
+    const size_t u2 = (size_t)b->long_elems * (b->prec == ge::kFP32C ? 2 : 1) *
+                      (b->prec == ge::kFP64 ? 8 : 4);
+    return 256 + (u2 + 255) / 256 * 256;
+}
+
+ge_status ge_batch_set_wait_polls(ge_batch_t b, int64_t polls)
+{
+    if (!b)
+        return fail(GE_ERR_INVALID, "ge_batch_set_wait_polls: batch is NULL");
+    if (polls < 0 || polls > (1 << 30))
+        return fail(GE_ERR_INVALID, "ge_batch_set_wait_polls: polls = %lld out of range",
+                    (long long)polls);
+    if (polls != b->wait_polls) {
+        drop_graphs(b);
+        b->wait_polls = (int)polls;
+    }
+    return GE_OK;
+}
+
+ge_status ge_batch_check(ge_batch_t b, void *stream)
+{
+    if (!b)
+        return fail(GE_ERR_INVALID, "ge_batch_check: batch is NULL");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "ge_batch_check: stream synchronize");
+    return take_status(b, "ge_batch_check");
+}
 
 }  // extern "C"
 
@@ -555,6 +660,47 @@ bool ge::batch_shape(ge_batch_t b, int64_t *nrods, const int64_t **n, int *prec)
     *prec = b->prec;
     return true;
 }
+
+namespace {
+
+// Kernel arguments of one run of the plan with queue head and second level
+// buffers at `work` (256-byte aligned: the head, then u2 from byte 256).
+ge::BatchArgs run_args(const ge_batch_s *b, void *u, void *work, int64_t step0, int64_t nsteps)
+{
+    ge::BatchArgs a{};
+    a.u = u;
+    a.rods = b->d_rods;
+    a.tasks = b->d_tasks;
+    a.counter = static_cast<int *>(work);
+    a.estride = b->estride;
+    a.step0 = step0 & 1;   // only the parity of the first level matters
+    a.nsteps = (int32_t)nsteps;
+    a.ntasks = b->ntasks;
+    a.sync = b->sync;
+    a.wait_polls = b->wait_polls;
+    a.status = b->status.dev;
+    a.u2 = b->has_long ? static_cast<char *>(work) + 256 : nullptr;
+    a.estride2 = b->estride2;
+    a.long_depth = kLongDepth;
+    a.long_halo = long_halo(b->prec);
+    return a;
+}
+
+// Checks shared by both run entry points; reports what earlier runs raised.
+ge_status check_run(ge_batch_s *b, void *u, int64_t step0, int64_t nsteps, const char *who)
+{
+    if (!b)
+        return fail(GE_ERR_INVALID, "%s: batch is NULL", who);
+    if (!u)
+        return fail(GE_ERR_INVALID, "%s: u must be given", who);
+    if ((uintptr_t)u & 15)
+        return fail(GE_ERR_INVALID, "%s: u must be 16-byte aligned", who);
+    if (step0 < 0 || nsteps < 0 || nsteps > (1 << 30))
+        return fail(GE_ERR_INVALID, "%s: step0/nsteps out of range", who);
+    return take_status(b, who);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -580,14 +726,14 @@ ge_status ge_batch_info(ge_batch_t b, int32_t *ntasks, int32_t *grid, double *es
 ge_status ge_solve_batch(ge_batch_t b, void *u, void *workspace, int64_t step0, int64_t nsteps,
                          void *stream)
 {
-    if (!b)
-        return fail(GE_ERR_INVALID, "ge_solve_batch: batch is NULL");
-    if (!u || !workspace)
-        return fail(GE_ERR_INVALID, "ge_solve_batch: u and workspace must be given");
-    if (((uintptr_t)u & 15) || ((uintptr_t)workspace & 255))
-        return fail(GE_ERR_INVALID, "ge_solve_batch: u must be 16-byte and workspace 256-byte aligned");
-    if (step0 < 0 || nsteps < 0 || nsteps > (1 << 30))
-        return fail(GE_ERR_INVALID, "ge_solve_batch: step0/nsteps out of range");
+    if (b && !workspace)
+        return fail(GE_ERR_INVALID, "ge_solve_batch: workspace must be given");
+    if ((uintptr_t)workspace & 255)
+        return fail(GE_ERR_INVALID, "ge_solve_batch: workspace must be 256-byte aligned");
+    {
+        const ge_status rs = check_run(b, u, step0, nsteps, "ge_solve_batch");
+        if (rs != GE_OK) return rs;
+    }
     if (nsteps == 0)
         return GE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -598,16 +744,7 @@ ge_status ge_solve_batch(ge_batch_t b, void *u, void *workspace, int64_t step0, 
         if (g.u == u && g.ws == workspace && g.parity == parity && g.nsteps == nsteps) slot = &g;
     }
     if (!slot) {
-        ge::BatchArgs a{};
-        a.u = u;
-        a.rods = b->d_rods;
-        a.tasks = b->d_tasks;
-        a.counter = static_cast<int *>(workspace);
-        a.estride = b->estride;
-        a.step0 = parity;   // only the parity of the first level matters
-        a.nsteps = (int32_t)nsteps;
-        a.ntasks = b->ntasks;
-        a.sync = b->sync;
+        const ge::BatchArgs a = run_args(b, u, workspace, parity, nsteps);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "ge_solve_batch: begin capture");

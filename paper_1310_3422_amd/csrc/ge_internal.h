@@ -26,6 +26,20 @@ int64_t comp_offset(int64_t n);
 // Rod count, points per rod and precision of a batch plan; false for NULL.
 bool batch_shape(ge_batch_t b, int64_t *nrods, const int64_t **n, int *prec);
 
+// Status words a plan's kernels may raise (StatusWord in ge_level.h): pinned,
+// mapped host memory, written by the kernels with plain stores and read by
+// the host without waiting for the device.  `dev` is the kernels' view.
+// Without a usable device the allocation fails and both pointers stay null.
+struct StatusWords {
+    int *host = nullptr;
+    int *dev = nullptr;
+};
+bool status_alloc(StatusWords &w);
+// Waits for the device (a kernel may still hold the pointer) and frees.
+void status_free(StatusWords &w);
+// True (and the word cleared) if a finished launch raised word `word`.
+bool status_take(StatusWords &w, int word);
+
 // Message recorded by the last set_error on the calling thread.
 const char *last_error_str();
 

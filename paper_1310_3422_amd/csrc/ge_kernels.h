@@ -8,6 +8,11 @@ namespace ge {
 
 enum Prec : int { kFP64 = 0, kFP32 = 1, kFP32C = 2 };
 
+// Status words a launch may raise (host-mapped memory owned by a plan): a
+// stored value was NaN or infinite; a wave's wait for a neighbouring wave
+// gave up (the launch's results are then not valid).
+enum StatusWord : int { kStatusNonfinite = 0, kStatusWaitGaveUp = 1, kStatusWords = 2 };
+
 // One launch of the tiled sweep: every workgroup loads a window of
 // W = NW*64*K consecutive points of one rod, advances it `nlev` levels in
 // registers and writes back its core of `core` points.
@@ -23,7 +28,8 @@ struct TileArgs {
     int64_t core;            // core points per tile
     int64_t ntiles;
     int64_t level0;          // global index of the first level of this launch
-    int64_t estride;         // FP32C: element offset of the e block (= n)
+    int64_t estride;         // FP32C: element offset of the e block of `in`
+    int64_t estride_out;     // FP32C: element offset of the e block of `out`
     int32_t halo;            // window points each side of the core
     int32_t nlev;            // levels advanced by this launch
     double c1, c2, cs;       // (r+r^2)/(1+2r), r^2/(1+2r), r/(1+r)
@@ -34,6 +40,9 @@ struct TileArgs {
     // couples (one per lane), nsdc of them in the rod
     int64_t nsdc;
     double ca;               // (1-r)/(1+r)
+    // host-mapped status words of the plan (StatusWord in ge_level.h), or
+    // null: a launch that stores a NaN or infinite value sets word 0
+    int *status;
 };
 
 // Supported (precision, points per lane, waves per workgroup) choices.

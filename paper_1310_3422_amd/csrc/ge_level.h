@@ -35,6 +35,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ge_kernels.h"
+
 namespace ge {
 namespace dev {
 
@@ -301,6 +303,35 @@ __device__ __forceinline__ T get_at(const T (&v)[K], int k, T otherwise)
     return r;
 }
 
+// Raise a status word (StatusWord, ge_kernels.h): host-mapped memory of the
+// plan, written with a plain system-scope store, so no read-modify-write
+// crosses the bus.
+__device__ __forceinline__ void raise_status(int *status, int word)
+{
+    __hip_atomic_store(status + word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Raise kStatusNonfinite when a value of the lane with global index in
+// [lo, hi) (the values the caller is about to store) is NaN or infinite.
+// One class test per value; at most one store per wave.
+template <typename T, int K, bool COMP>
+__device__ __forceinline__ void check_finite(int *status, const T (&s)[K], const T (&e)[K],
+                                             int64_t g0, int64_t lo, int64_t hi)
+{
+    if (!status) return;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool in = g0 + j >= lo && g0 + j < hi;
+        bool nf = !__builtin_isfinite(s[j]);
+        if constexpr (COMP) nf = nf || !__builtin_isfinite(e[j]);
+        bad = bad || (in && nf);
+    }
+    const uint64_t m = __ballot(bad);
+    if (m != 0 && (threadIdx.x & (kWave - 1)) == (unsigned)__builtin_ctzll(m))
+        raise_status(status, kStatusNonfinite);
+}
+
 // A first difference: one value, or the (s, e) parts of the pair kept apart.
 template <typename T, bool COMP> struct Dif { T s; };
 template <typename T> struct Dif<T, true> { T s, e; };
@@ -369,23 +400,52 @@ struct FluxTap {
     double tau, h, gln;
 };
 
+// The source weight of every point of the lane at parity P,
+// B_i = e1 b_i + e2 b_q with q the partner of i (neighbouring lanes' points
+// through bl = b_{-1}, br = b_K), formed by the same expression the
+// per-level update uses; a launch's profile is fixed, so these are formed
+// once per launch and each level adds a(t) B_i with one FMA.
+template <typename T, int K, int P>
+__device__ __forceinline__ void source_weights(const T (&b)[K], T bl, T br, const Coef<T> &c,
+                                               T (&B)[K])
+{
+    if constexpr (P == 0) {
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q) {
+            B[2 * q] = fmaT(c.e1, b[2 * q], c.e2 * b[2 * q + 1]);
+            B[2 * q + 1] = fmaT(c.e1, b[2 * q + 1], c.e2 * b[2 * q]);
+        }
+    } else {
+        B[0] = fmaT(c.e1, b[0], c.e2 * bl);
+#pragma unroll
+        for (int q = 1; q < K / 2; ++q) {
+            const int j = 2 * q - 1;
+            B[j] = fmaT(c.e1, b[j], c.e2 * b[j + 1]);
+            B[j + 1] = fmaT(c.e1, b[j + 1], c.e2 * b[j]);
+        }
+        B[K - 1] = fmaT(c.e1, b[K - 1], c.e2 * br);
+    }
+}
+
 // Advance the K points of every lane by one level of parity P (known at
 // compile time: a runtime parity would merge the two groupings' results for
 // every point each level and cost the register file).
 //   s, e : the lane's points (e is the compensation of the pair, else 0)
-//   b    : the lane's source profile; bl, br: profile of u_{-1} and u_K
+//   b    : SRC = 1: the lane's source profile, bl, br: profile of u_{-1}
+//          and u_K; SRC = 2: the weights of this parity (source_weights)
 //   xl, xl2, xr, xr2 : u_{-1}, u_{-2}, u_K, u_{K+1} for lanes 0 / 63 (DPP
 //          fill from the neighbouring waves, a wall value, or anything at
 //          an open window edge); yl.. the same for e
 // WALL instantiations apply the lone-point formulas and the flux tap; every
 // other point of every instantiation evaluates the same expressions.  OPEN:
 // both edges of the wave are open window edges, so the fills are not used.
-template <typename T, int K, bool COMP, bool SRC, bool WALL, int P, bool OPEN = false>
+template <typename T, int K, bool COMP, int SRC, bool WALL, int P, bool OPEN = false>
 __device__ __forceinline__ void ge_level(T (&s)[K], T (&e)[K], const T (&b)[K], T bl, T br,
                                          T xl, T xl2, T xr, T xr2, T yl, T yl2, T yr, T yr2,
                                          const Coef<T> &c, T an,
                                          const WallLevel<T> &wl, FluxTap &ft)
 {
+    static_assert(!(WALL && SRC == 2), "wall tiles take the source from the profile");
     const T c1 = c.c1, c2 = c.c2, cs = c.cs, e1 = c.e1, e2 = c.e2, es = c.es;
     // u_{-1} and u_K: neighbour lanes' edge points
     const T sl = edge_left<OPEN>(xl, s[K - 1]), sr = edge_right<OPEN>(xr, s[0]);
@@ -398,7 +458,8 @@ __device__ __forceinline__ void ge_level(T (&s)[K], T (&e)[K], const T (&b)[K], 
     auto upd = [&](int j, T Ds, T Dp, T bp) {
         if constexpr (COMP) {
             T inc = fmaT(c1, Ds, c2 * Dp);
-            if constexpr (SRC) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
+            if constexpr (SRC == 1) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
+            if constexpr (SRC == 2) inc = fmaT(an, b[j], inc);
             if constexpr (WALL) {
                 if (j == 0) {
                     T alt = cs * (Ds + wl.dgl);
@@ -414,7 +475,8 @@ __device__ __forceinline__ void ge_level(T (&s)[K], T (&e)[K], const T (&b)[K], 
         } else if constexpr (sizeof(T) == 8) {
             // FP64: two fused steps, u + c1 D_self, then + c2 D_partner
             T t = fmaT(c1, Ds, s[j]);
-            if constexpr (SRC) t = fmaT(an, fmaT(e1, b[j], e2 * bp), t);
+            if constexpr (SRC == 1) t = fmaT(an, fmaT(e1, b[j], e2 * bp), t);
+            if constexpr (SRC == 2) t = fmaT(an, b[j], t);
             T v = fmaT(c2, Dp, t);
             if constexpr (WALL) {
                 if (j == 0) {
@@ -427,7 +489,8 @@ __device__ __forceinline__ void ge_level(T (&s)[K], T (&e)[K], const T (&b)[K], 
         } else {
             // FP32: form the increment first, so u is rounded once per level
             T inc = fmaT(c1, Ds, c2 * Dp);
-            if constexpr (SRC) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
+            if constexpr (SRC == 1) inc = fmaT(an, fmaT(e1, b[j], e2 * bp), inc);
+            if constexpr (SRC == 2) inc = fmaT(an, b[j], inc);
             if constexpr (WALL) {
                 if (j == 0) {
                     T alt = cs * (Ds + wl.dgl);

@@ -7,7 +7,7 @@
 namespace ge {
 namespace nn {
 
-enum Epi : int { kEpiGelu = 0, kEpiGeluRes = 1, kEpiOut = 2, kEpiBwd = 3 };
+enum Epi : int { kEpiGelu = 0, kEpiGeluRes = 1, kEpiOut = 2, kEpiBwd = 3, kEpiF32 = 4 };
 
 struct ConvArgs {
     const void *x;        // bf16 [batch][width][cin]
@@ -17,7 +17,7 @@ struct ConvArgs {
     int dil;              // tap spacing d: taps at offsets (k - 2) d, 1 <= d <= kMaxDil
     void *pre_out;        // bf16 [..][cout]  (kEpiGelu*; null: not stored)
     void *act_out;        // bf16 [..][cout]  (kEpiGelu*)
-    float *out_f32;       // f32 [batch][width] (kEpiOut)
+    float *out_f32;       // f32 [batch][width] (kEpiOut), [batch][width][cout] (kEpiF32)
     const void *res_in;   // bf16 [..][cout]  (kEpiBwd, or null)
     const void *pre_in;   // bf16 [..][cout]  (kEpiBwd)
     void *gh_out;         // bf16 [..][cout]  (kEpiBwd, or null)

@@ -42,6 +42,8 @@ constexpr int kThreads = 256;     // 4 waves, 32 positions each
 //   kEpiOut     : out_f32[b][w] = acc + bias (channel 0)
 //   kEpiBwd     : gh = acc (+ res_in) -> gh_out (bf16, optional);
 //                 gp_out = bf16(gh) * gelu'(pre_in) (bf16)
+//   kEpiF32     : out_f32[b][w][o] = acc + bias, every channel, unrounded
+//                 (the per-layer probe that checks the products)
 // LDS rows are padded by 16 bytes so that 16 lanes reading 16 bytes from 16
 // consecutive rows hit distinct banks.
 template <int CIN, int COUT, int EPI>
@@ -141,6 +143,8 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a)
                 *reinterpret_cast<bf16x4 *>(&static_cast<bf16 *>(a.act_out)[o]) = act;
             } else if constexpr (EPI == kEpiOut) {
                 if (ch0 == 0) a.out_f32[rowbase + w] = v[0];
+            } else if constexpr (EPI == kEpiF32) {
+                *reinterpret_cast<float4 *>(&a.out_f32[o]) = float4{v[0], v[1], v[2], v[3]};
             } else {   // kEpiBwd
                 bf16x4 gh, gp;
                 const bf16x4 pre = *reinterpret_cast<const bf16x4 *>(
@@ -491,6 +495,9 @@ hipError_t launch_conv(int cin, int cout, int epi, const ConvArgs &a, int batch,
     GE_CONV(64, 16, kEpiOut)
     GE_CONV(32, 64, kEpiBwd)
     GE_CONV(64, 64, kEpiBwd)
+    GE_CONV(32, 64, kEpiF32)
+    GE_CONV(64, 64, kEpiF32)
+    GE_CONV(64, 16, kEpiF32)
 #undef GE_CONV
     return hipErrorInvalidValue;
 }

@@ -406,6 +406,58 @@ ge_status ge_nn_train_step(ge_nn_t n, const float *u, const float *u64, const fl
     return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_train_step: %s", hipGetErrorString(e));
 }
 
+ge_status ge_nn_layer_shape(int32_t layer, int32_t *ci, int32_t *co, int32_t *cip,
+                            int32_t *cop, int32_t *cod, int32_t *dil)
+{
+    if (layer < 1 || layer > 6)
+        return fail(GE_ERR_INVALID, "ge_nn_layer_shape: layer %d outside 1..6", layer);
+    const Layer &L = kLayers[layer - 1];
+    if (ci) *ci = L.ci;
+    if (co) *co = L.co;
+    if (cip) *cip = L.cip;
+    if (cop) *cop = L.cop;
+    if (cod) *cod = L.cod;
+    if (dil) *dil = L.dil;
+    return GE_OK;
+}
+
+ge_status ge_nn_layer_probe(ge_nn_t n, int32_t layer, int32_t op, const void *x, const void *g,
+                            int32_t batch, float *out, void *stream)
+{
+    ge_status st = check_io(n, batch, "ge_nn_layer_probe");
+    if (st != GE_OK) return st;
+    if (layer < 1 || layer > 6)
+        return fail(GE_ERR_INVALID, "ge_nn_layer_probe: layer %d outside 1..6", layer);
+    if (!out) return fail(GE_ERR_INVALID, "ge_nn_layer_probe: out is NULL");
+    const int l = layer - 1;
+    const Layer &L = kLayers[l];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (op == 0 || op == 1) {
+        if (op == 0 ? !x : !g) return fail(GE_ERR_INVALID, "ge_nn_layer_probe: input is NULL");
+        if (op == 1 && l == 0)
+            return fail(GE_ERR_INVALID, "ge_nn_layer_probe: layer 1 has no input gradient");
+        ConvArgs a{};
+        a.x = op == 0 ? x : g;
+        a.w = op == 0 ? n->wf[l] : n->wd[l];
+        a.bias = op == 0 ? n->bf[l] : nullptr;
+        a.width = n->width;
+        a.dil = L.dil;
+        a.out_f32 = out;
+        e = op == 0 ? launch_conv(L.cip, L.cop, kEpiF32, a, batch, s)
+                    : launch_conv(L.cod, L.cip, kEpiF32, a, batch, s);
+    } else if (op == 2) {
+        if (!x || !g) return fail(GE_ERR_INVALID, "ge_nn_layer_probe: x and g must be given");
+        const int nb = wgrad_blocks(n, batch);
+        WgradArgs wa{x, g, n->wpart, n->width, batch, L.dil};
+        e = launch_wgrad(L.cip, L.cod, wa, nb, s);
+        if (e == hipSuccess) e = launch_wgrad_reduce(n->wpart, nb, L.cip, L.cod, L.ci, L.co, out, s);
+    } else {
+        return fail(GE_ERR_INVALID, "ge_nn_layer_probe: op %d is not 0, 1 or 2", op);
+    }
+    return e == hipSuccess ? GE_OK : fail(GE_ERR_HIP, "ge_nn_layer_probe: %s", hipGetErrorString(e));
+}
+
 ge_status ge_f32_to_f64(const float *x, double *y, int64_t n, void *stream)
 {
     if (n < 0 || (n > 0 && (!x || !y))) return fail(GE_ERR_INVALID, "ge_f32_to_f64: bad arguments");

@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kWave) void sdc_tile_kernel(TileArgs a)
                                          (T)gr(lev + 1));
     });
     const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
+    check_finite<T, K, false>(a.status, s, s, i * K, c0 * K, c1 * K < a.n ? c1 * K : a.n);
     stage_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds, s);
 }
 
@@ -493,6 +494,9 @@ __global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int n
             sdc_level<T, K, p == 0 ? 1 : 2>(s, cf, first, last, (T)gl(lev), (T)gl(lev + 1),
                                              (T)gr(lev + 1));
         });
+        const int64_t c0 = t * a.core;
+        const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
+        check_finite<T, K, false>(a.status, s, s, i * K, c0 * K, c1 * K < a.n ? c1 * K : a.n);
         if (more) {
             wait_vmem();
             tail_fix<T, K>(in, wstart(tn) * K, a.n, lds);
@@ -500,8 +504,6 @@ __global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int n
         } else {
             rows_write<T, K>(lds, s);
         }
-        const int64_t c0 = t * a.core;
-        const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
         chunks_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds);
         if (!more)
             break;

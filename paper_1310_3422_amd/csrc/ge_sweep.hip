@@ -11,192 +11,12 @@
 // exchanged, and no data crosses workgroups inside a launch.
 #include "ge_kernels.h"
 #include "ge_level.h"
+#include "ge_tile.h"
 
 namespace ge {
 namespace {
 
 using namespace dev;
-
-// The lane's points of the window starting at ws (and their compensation
-// and source profile where the form has them); guarded at a wall.
-template <typename T, int K, bool COMP, bool SRC, bool WALL>
-__device__ __forceinline__ void load_tile(const TileArgs &a, int64_t ws, T (&s)[K], T (&e)[K],
-                                          T (&b)[K])
-{
-    const int64_t g0 = ws + (int64_t)threadIdx.x * K;
-    const T *in_s = static_cast<const T *>(a.in);
-    const T *in_e = in_s + a.estride;
-    const T *srcb = static_cast<const T *>(a.src_b);
-    if constexpr (WALL) {
-        load_lane_guarded<T, K>(in_s + g0, g0, a.n, s);
-        if constexpr (COMP) load_lane_guarded<T, K>(in_e + g0, g0, a.n, e);
-        if constexpr (SRC) load_lane_guarded<T, K>(srcb + g0, g0, a.n, b);
-    } else {
-        load_lane<T, K>(in_s + g0, s);
-        if constexpr (COMP) load_lane<T, K>(in_e + g0, e);
-        if constexpr (SRC) load_lane<T, K>(srcb + g0, b);
-    }
-    if constexpr (!COMP) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) e[j] = T(0);
-    }
-}
-
-// Advance the loaded window of tile t (start ws) by the launch's levels and
-// store its core.
-template <typename T, int K, int NW, bool COMP, bool SRC, bool WALL>
-__device__ __forceinline__ void sweep_tile(const TileArgs &a, int64_t t, int64_t ws, T (&s)[K],
-                                           T (&e)[K], const T (&b)[K])
-{
-    constexpr int W = NW * kWave * K;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1);
-    // the wave index is uniform across the wave: let the compiler keep
-    // everything derived from it in scalar registers
-    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int64_t n = a.n;
-    const int64_t core_lo = t * a.core;
-    const int64_t core_hi = min(core_lo + a.core, n);
-    const int64_t g0 = ws + (int64_t)tid * K;       // global index of my first point
-
-    T *out_s = static_cast<T *>(a.out);
-    T *out_e = out_s + a.estride;
-
-    __shared__ T xs[2][NW][4];
-    __shared__ T xe[2][NW][4];
-    __shared__ T xb[NW][2];
-
-    // source profile of the neighbours' edge points (fixed for the launch)
-    T bl = T(0), br = T(0);
-    if constexpr (SRC) {
-        bl = from_left(T(0), b[K - 1]);
-        br = from_right(T(0), b[0]);
-        if constexpr (NW > 1) {
-            if (lane == 0) xb[w][0] = b[0];
-            if (lane == kWave - 1) xb[w][1] = b[K - 1];
-            __syncthreads();
-            if (lane == 0 && w > 0) bl = xb[w - 1][1];
-            if (lane == kWave - 1 && w < NW - 1) br = xb[w + 1][0];
-        }
-    }
-
-    // wall geometry (uniform over the workgroup)
-    const bool left_wall = WALL && (ws == 0);
-    const int64_t qR = n - ws;                     // window position of the right wall node
-    const bool ghost_in = WALL && (qR < W);
-    const bool ghost_edge = WALL && (qR == W);
-    const int kR = (int)(ghost_in ? (qR % K) : 0);
-    const int lR = (int)(ghost_in ? (qR / K) : -1);          // thread holding it
-    const int64_t qS = qR - 1;                     // window position of point n-1
-    const bool has_S = WALL && (qS >= 0) && (qS < W);
-    const int kS = (int)(has_S ? (qS % K) : 0);
-    const int lS = (int)(has_S ? (qS / K) : -1);
-    const bool flux_on = WALL && (a.flux != nullptr);
-    const bool own_L = flux_on && left_wall && core_lo == 0;
-    const bool own_R = flux_on && has_S && (n - 1 >= core_lo) && (n - 1 < core_hi);
-    double accL = 0.0, accR = 0.0;
-    if (own_L) accL = a.flux[0];
-    if (own_R) accR = a.flux[1];
-
-    const Coef<T> cf = lane_coef(Coef<T>{(T)a.c1, (T)a.c2, (T)a.cs, (T)a.e1, (T)a.e2, (T)a.es});
-    FluxTap ft{own_L && tid == 0, accL, a.tau, a.h, 0.0};
-
-    for_levels(a.level0, a.nlev, [&](auto par, int lev) {
-        constexpr int p = decltype(par)::value;
-        double glo = a.gl0, gln = a.gl0, gro = a.gr0, grn = a.gr0;
-        if constexpr (WALL) {
-            if (a.gl_t) { glo = a.gl_t[lev]; gln = a.gl_t[lev + 1]; }
-            if (a.gr_t) { gro = a.gr_t[lev]; grn = a.gr_t[lev + 1]; }
-            if (ghost_in) {
-                T gh, gl_;
-                split_wall<T, COMP>(gro, gh, gl_);
-                put_at<T, K>(s, kR, tid == lR, gh);
-                if constexpr (COMP) put_at<T, K>(e, kR, tid == lR, gl_);
-            }
-        }
-
-        // Values entering the wave at its edges: from the neighbouring waves
-        // through LDS, or (at an open window edge) anything -- those points
-        // lie in the halo.  They ride in as the DPP fill of lanes 0 and 63.
-        T xl = T(0), xl2 = T(0), xr = T(0), xr2 = T(0);
-        T yl = T(0), yl2 = T(0), yr = T(0), yr2 = T(0);
-        if constexpr (NW > 1) {
-            const int pb = lev & 1;
-            if (lane == 0) { xs[pb][w][0] = s[0]; xs[pb][w][1] = s[1]; }
-            if (lane == kWave - 1) { xs[pb][w][2] = s[K - 2]; xs[pb][w][3] = s[K - 1]; }
-            if constexpr (COMP) {
-                if (lane == 0) { xe[pb][w][0] = e[0]; xe[pb][w][1] = e[1]; }
-                if (lane == kWave - 1) { xe[pb][w][2] = e[K - 2]; xe[pb][w][3] = e[K - 1]; }
-            }
-            __syncthreads();
-            const int wl = w > 0 ? w - 1 : 0, wr = w < NW - 1 ? w + 1 : NW - 1;
-            xl = xs[pb][wl][3]; xr = xs[pb][wr][0];
-            xl2 = xs[pb][wl][2]; xr2 = xs[pb][wr][1];
-            if constexpr (COMP) {
-                yl = xe[pb][wl][3]; yr = xe[pb][wr][0];
-                yl2 = xe[pb][wl][2]; yr2 = xe[pb][wr][1];
-            }
-        }
-        WallLevel<T> wlv{false, T(0)};
-        T gr_hi = T(0), gr_lo = T(0), dgr = T(0);
-        bool singR = false;
-        if constexpr (WALL) {
-            if (left_wall && w == 0) {
-                T gh, glw;
-                split_wall<T, COMP>(glo, gh, glw);
-                xl = gh;
-                if constexpr (COMP) yl = glw;
-            }
-            if (ghost_edge && w == NW - 1) {
-                T gh, glw;
-                split_wall<T, COMP>(gro, gh, glw);
-                xr = gh;
-                if constexpr (COMP) yr = glw;
-            }
-            wlv.dgl = (T)(gln - glo);
-            wlv.isL = left_wall && (p == 1) && (tid == 0);
-            ft.gln = gln;
-            split_wall<T, COMP>(gro, gr_hi, gr_lo);
-            dgr = (T)(grn - gro);
-            singR = has_S && (((n - 1 + p) & 1) == 0);
-        }
-        const T an = SRC ? (T)a.src_a[lev] : T(0);
-        Lone<T> lone{T(0), T(0)};
-        if (WALL && singR)
-            lone = right_lone<T, K, COMP, SRC>(s, e, b, kS, xl, yl, gr_hi, gr_lo, dgr, cf, an);
-        ge_level<T, K, COMP, SRC, WALL, p, NW == 1 && !WALL>(s, e, b, bl, br, xl, xl2, xr, xr2,
-                                                             yl, yl2, yr, yr2, cf, an, wlv, ft);
-        if (WALL && singR) {
-            put_at<T, K>(s, kS, tid == lS, lone.s);
-            if constexpr (COMP) put_at<T, K>(e, kS, tid == lS, lone.e);
-        }
-        if (WALL && own_R) {
-            // wall first difference at the new level, accumulated in FP64
-            const double v = (double)get_at<T, K>(s, kS, T(0)) +
-                             (COMP ? (double)get_at<T, K>(e, kS, T(0)) : 0.0);
-            if (tid == lS) accR = accR + a.tau * (v - grn) / a.h;
-        }
-    });
-    accL = ft.accL;
-
-    if (own_L && tid == 0) a.flux[0] = accL;
-    if (own_R && tid == lS) a.flux[1] = accR;
-
-    if constexpr (WALL) {
-        store_lane_guarded<T, K>(out_s + g0, g0, core_lo, core_hi, s);
-        if constexpr (COMP) store_lane_guarded<T, K>(out_e + g0, g0, core_lo, core_hi, e);
-    } else {
-        store_lane_chunks<T, K>(out_s + g0, g0, core_lo, core_hi, s);
-        if constexpr (COMP) store_lane_chunks<T, K>(out_e + g0, g0, core_lo, core_hi, e);
-    }
-}
-
-template <typename T, int K, int NW, bool COMP, bool SRC, bool WALL>
-__device__ __forceinline__ void run_tile(const TileArgs &a, int64_t t, int64_t ws)
-{
-    T s[K], e[K], b[K];
-    load_tile<T, K, COMP, SRC, WALL>(a, ws, s, e, b);
-    sweep_tile<T, K, NW, COMP, SRC, WALL>(a, t, ws, s, e, b);
-}
 
 template <typename T, int K, int NW, bool COMP, bool SRC>
 __global__ __launch_bounds__(NW *kWave) void tile_kernel(TileArgs a)
@@ -211,9 +31,9 @@ __global__ __launch_bounds__(NW *kWave) void tile_kernel(TileArgs a)
     constexpr int64_t W = NW * kWave * K;
     const bool wall = (ws == 0) || (ws + W >= a.n);
     if (wall)
-        run_tile<T, K, NW, COMP, SRC, true>(a, t, ws);
+        run_tile<T, K, NW, COMP, SRC, true>(a, threadIdx.x, t, ws);
     else
-        run_tile<T, K, NW, COMP, SRC, false>(a, t, ws);
+        run_tile<T, K, NW, COMP, SRC, false>(a, threadIdx.x, t, ws);
 }
 
 // First tile whose window reaches the right wall (tiles from there on, and
@@ -240,7 +60,7 @@ __global__ __launch_bounds__(kWave) void tile_persistent_kernel(TileArgs a, int 
     if (g >= nint) {
         const int64_t t = g == nint ? 0 : tw + (g - nint - 1);
         if (t < a.ntiles && (t == 0 || t >= tw))
-            run_tile<T, K, 1, COMP, SRC, true>(a, t, t == 0 ? 0 : t * a.core - a.halo);
+            run_tile<T, K, 1, COMP, SRC, true>(a, threadIdx.x, t, t == 0 ? 0 : t * a.core - a.halo);
         return;
     }
     const int per = nint / 8;
@@ -252,7 +72,7 @@ __global__ __launch_bounds__(kWave) void tile_persistent_kernel(TileArgs a, int 
     // prefetch registers, so the loads pending during a sweep are only the
     // next tile's and the sweep never waits for them
     T s[K], e[K], b[K], ns[K], ne[K], nb[K];
-    load_tile<T, K, COMP, SRC, false>(a, t * a.core - a.halo, ns, ne, nb);
+    load_tile<T, K, COMP, SRC, false>(a, threadIdx.x, t * a.core - a.halo, ns, ne, nb);
     for (;;) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
@@ -262,8 +82,8 @@ __global__ __launch_bounds__(kWave) void tile_persistent_kernel(TileArgs a, int 
         }
         const int64_t tn = t + nint;
         if (tn < tw)
-            load_tile<T, K, COMP, SRC, false>(a, tn * a.core - a.halo, ns, ne, nb);
-        sweep_tile<T, K, 1, COMP, SRC, false>(a, t, t * a.core - a.halo, s, e, b);
+            load_tile<T, K, COMP, SRC, false>(a, threadIdx.x, tn * a.core - a.halo, ns, ne, nb);
+        sweep_tile<T, K, 1, COMP, SRC, false>(a, threadIdx.x, t, t * a.core - a.halo, s, e, b);
         if (tn >= tw)
             break;
         t = tn;

@@ -13,7 +13,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libge.so")
 
-GE_OK, GE_ERR_INVALID, GE_ERR_NOMEM, GE_ERR_HIP, GE_ERR_UNSUPPORTED, GE_ERR_NONFINITE = range(6)
+(GE_OK, GE_ERR_INVALID, GE_ERR_NOMEM, GE_ERR_HIP, GE_ERR_UNSUPPORTED, GE_ERR_NONFINITE,
+ GE_ERR_SYNC) = range(7)
 GE_FP64, GE_FP32, GE_FP32_COMP = 0, 1, 2
 PRECISIONS = {"fp64": GE_FP64, "fp32": GE_FP32, "fp32c": GE_FP32_COMP}
 
@@ -58,6 +59,7 @@ _SIGS = {
     "ge_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(GeDesc)]),
     "ge_plan": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GeDesc)]),
     "ge_destroy": (None, [_vp]),
+    "ge_plan_check": (ctypes.c_int, [_vp, _vp]),
     "ge_step_n": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp]),
     "ge_plan_config": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -70,6 +72,8 @@ _SIGS = {
     "ge_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                      ctypes.POINTER(_dbl), _vp]),
     "ge_solve_batch": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
+    "ge_batch_set_wait_polls": (ctypes.c_int, [_vp, _i64]),
+    "ge_batch_check": (ctypes.c_int, [_vp, _vp]),
     "ge_plan_schedule": (_i32, [_vp]),
     "ge_nn_param_count": (_i64, []),
     "ge_nn_create": (ctypes.c_int, [ctypes.POINTER(_vp), _i32, _i32, ctypes.c_uint64]),
@@ -83,6 +87,8 @@ _SIGS = {
     "ge_nn_train_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, _vp, _vp]),
     "ge_nn_advance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i32, _i32, _dbl,
                                      _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
+    "ge_nn_layer_shape": (ctypes.c_int, [_i32] + [ctypes.POINTER(_i32)] * 6),
+    "ge_nn_layer_probe": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp]),
     "ge_2d_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Ge2dDesc)]),
     "ge_2d_step_n": (ctypes.c_int, [ctypes.POINTER(Ge2dDesc), _vp, _vp, _i64, _i64, _vp]),
     "ge_f32_to_f64": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
@@ -220,6 +226,11 @@ class Plan:
                               _stream_ptr(stream)))
         return u
 
+    def check(self, stream=None):
+        """ge_plan_check: wait for the stream; raise GEError(GE_ERR_NONFINITE)
+        if a launch of this plan stored a NaN or infinite value."""
+        check(lib().ge_plan_check(self.handle, _stream_ptr(stream)))
+
 
 def comp_to_fp64(pair, n, stream=None):
     torch = _torch()
@@ -323,6 +334,14 @@ class Batch:
         check(lib().ge_solve_batch(self.handle, _ptr(u), _ptr(workspace), int(step0),
                                    int(nsteps), _stream_ptr(stream)))
         return u
+
+    def set_wait_polls(self, polls):
+        check(lib().ge_batch_set_wait_polls(self.handle, int(polls)))
+
+    def check(self, stream=None):
+        """ge_batch_check: wait for the stream; raise GEError with GE_ERR_SYNC
+        or GE_ERR_NONFINITE if a run raised one."""
+        check(lib().ge_batch_check(self.handle, _stream_ptr(stream)))
 
 
 def pack_batch_state(rb_u0, offsets, n, precision, device="cuda"):
@@ -433,6 +452,32 @@ class Net:
             int(njumps), int(check), float(tol), _ptr(accepted), _ptr(fallbacks),
             _ptr(last_err), ctypes.byref(nfb), _stream_ptr(stream)))
         return int(nfb.value)
+
+    @staticmethod
+    def layer_shape(layer):
+        """(ci, co, cip, cop, cod, dil) of layer 1..6 (ge_nn_layer_shape)."""
+        v = [_i32() for _ in range(6)]
+        check(lib().ge_nn_layer_shape(int(layer), *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def layer_probe(self, layer, op, batch, x=None, g=None, stream=None):
+        """ge_nn_layer_probe: one product of one layer on bfloat16 operands
+        (torch.bfloat16 CUDA tensors, channels last, padded channels zero),
+        returned in FP32: op 0 forward [batch, width, cop], op 1 input
+        gradient [batch, width, cip], op 2 weight gradient (flat dW, db)."""
+        torch = _torch()
+        ci, co, cip, cop, cod, dil = self.layer_shape(layer)
+        for t, c, name in ((x, cip, "x"), (g, cod, "g")):
+            if t is not None and (not t.is_cuda or t.dtype != torch.bfloat16 or
+                                  not t.is_contiguous() or t.numel() != batch * self.width * c):
+                raise ValueError(f"{name} must be a contiguous bfloat16 CUDA tensor "
+                                 f"[{batch}, {self.width}, {c}]")
+        shape = {0: (batch, self.width, cop), 1: (batch, self.width, cip),
+                 2: (5 * co * ci + co,)}[int(op)]
+        out = torch.empty(shape, dtype=torch.float32, device="cuda")
+        check(lib().ge_nn_layer_probe(self.handle, int(layer), int(op), _ptr(x), _ptr(g),
+                                      int(batch), _ptr(out), _stream_ptr(stream)))
+        return out
 
     def train_step(self, u, u64, r, lr, loss=None, stream=None):
         b = r.numel()

@@ -40,6 +40,8 @@ def test_every_declared_symbol_is_exported():
 def test_status_strings_and_version():
     assert ge.status_str(0) == "GE_OK"
     assert ge.status_str(5) == "GE_ERR_NONFINITE"
+    assert ge.status_str(6) == "GE_ERR_SYNC"
+    assert ge.lib().ge_plan_check(None, None) == ge.GE_ERR_INVALID
     assert ge.lib().ge_version().decode().count(".") == 2
 
 
@@ -181,10 +183,8 @@ def _batch_desc(n, offsets, r=None, gl=None, gr=None, precision=1, tune=0, sync=
     (dict(n=[100, 50], offsets=[0, 102, 200]), ge.GE_ERR_INVALID),       # not a multiple of 4
     (dict(n=[100, 50], offsets=[0, 100, 200], r=[1.0, 0.0]), ge.GE_ERR_INVALID),
     (dict(n=[100, 50], offsets=[0, 100, 200], r=[1.0, float("nan")]), ge.GE_ERR_NONFINITE),
-    (dict(n=[70000], offsets=[0, 70000]), ge.GE_ERR_UNSUPPORTED),        # above FP32 on-chip limit
     (dict(n=[100], offsets=[0, 100], sync=4), ge.GE_ERR_INVALID),
     (dict(n=[100], offsets=[0, 100], sync=-1), ge.GE_ERR_INVALID),
-    (dict(n=[40000], offsets=[0, 40000], precision=0), ge.GE_ERR_UNSUPPORTED),
     (dict(n=[100], offsets=[0, 100], precision=9), ge.GE_ERR_INVALID),
 ])
 def test_batch_plan_rejects(case, status):
@@ -198,6 +198,8 @@ def test_batch_null_arguments():
     lib = ge.lib()
     assert lib.ge_batch_plan(None, None) == ge.GE_ERR_INVALID
     assert lib.ge_solve_batch(None, None, None, 0, 1, None) == ge.GE_ERR_INVALID
+    assert lib.ge_batch_check(None, None) == ge.GE_ERR_INVALID
+    assert lib.ge_batch_set_wait_polls(None, 5) == ge.GE_ERR_INVALID
     assert lib.ge_batch_state_elems(None) == -1
     assert lib.ge_batch_workspace_bytes(None) == 0
     lib.ge_batch_destroy(None)

@@ -182,3 +182,69 @@ def test_training_lowers_the_loss():
     last = float(net.grads(ud, u64d, rd)[0].cpu()[0])
     print(f"loss {first:.4e} -> {last:.4e}")
     assert last < 0.1 * first
+
+
+# One FP32 addition errs by at most 2^-24 of its result with rounding to
+# nearest; 2^-23 leaves room for a matrix core that truncates.  A sum of K
+# products, each exact in FP32 (bfloat16 x bfloat16), then differs from the
+# exact sum by at most (K - 1) u sum|terms| in any order of additions.
+ACC_U = 2.0 ** -23
+
+
+def _bf16_dev(a):
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+    return t.to(torch.bfloat16).cuda().contiguous()
+
+
+def _within_acc_bound(got, want, mag, k, what):
+    err = np.abs(got - want)
+    bound = (k - 1) * ACC_U * mag
+    worst = float(np.max(err / np.maximum(ACC_U * mag, 1e-300)))
+    print(f"{what}: K = {k}, max |err| / (u sum|terms|) = {worst:.2f}")
+    assert np.all(err <= bound + 1e-300), (what, float(np.max(err - bound)))
+
+
+@pytest.mark.parametrize("layer", [1, 2, 3, 4, 5, 6])
+def test_layer_products_match_oracle_on_the_same_bf16_operands(layer):
+    """Each layer's forward product, input gradient and weight gradient on
+    the matrix cores, in FP32 before any rounding (ge_nn_layer_probe),
+    against the FP64 oracle fed the same bfloat16 operands (inputs, output
+    gradients and the network's bfloat16-packed weights), element by
+    element within the bound of K FP32 additions: K = 5 c_in (+ the bias)
+    forward, 5 c_out for the input gradient, and batch x width positions
+    for the weight and bias gradients (partial sums reduced in a fixed
+    order).  Padded channels stay zero."""
+    width, batch = 512, 3
+    params = fp32_params(11)
+    net = make_net(width, batch, params)
+    ci, co, cip, cop, cod, dil = ge.Net.layer_shape(layer)
+    assert dil == cr.DILATIONS[layer - 1] and (ci, co) == cr.LAYERS[layer - 1]
+    w, b = params[layer - 1]
+    wb = cr.bf16(w)
+    rng = np.random.default_rng(layer)
+    x = np.zeros((batch, width, cip))
+    x[:, :, :ci] = cr.bf16(rng.standard_normal((batch, width, ci)))
+    g = np.zeros((batch, width, cod))
+    g[:, :, :co] = cr.bf16(1e-3 * rng.standard_normal((batch, width, co)))
+    xd, gd = _bf16_dev(x), _bf16_dev(g)
+    xr, gr = x[:, :, :ci], g[:, :, :co]
+
+    fwd = net.layer_probe(layer, 0, batch, x=xd).cpu().numpy().astype(np.float64)
+    assert fwd.shape == (batch, width, cop) and not np.any(fwd[:, :, co:])
+    _within_acc_bound(fwd[:, :, :co], cr.conv(xr, wb, dil) + b,
+                      cr.conv(np.abs(xr), np.abs(wb), dil) + np.abs(b), 5 * ci + 1,
+                      f"layer {layer} forward")
+    if layer > 1:
+        dx = net.layer_probe(layer, 1, batch, g=gd).cpu().numpy().astype(np.float64)
+        assert dx.shape == (batch, width, cip)
+        _within_acc_bound(dx[:, :, :ci], cr.conv_input_grad(gr, wb, dil),
+                          cr.conv_input_grad(np.abs(gr), np.abs(wb), dil), 5 * co,
+                          f"layer {layer} input gradient")
+    flat = net.layer_probe(layer, 2, batch, x=xd, g=gd).cpu().numpy().astype(np.float64)
+    dw, db = flat[:5 * co * ci].reshape(5, co, ci), flat[5 * co * ci:]
+    npos = batch * width
+    _within_acc_bound(dw, cr.conv_weight_grad(xr, gr, dil),
+                      cr.conv_weight_grad(np.abs(xr), np.abs(gr), dil), npos,
+                      f"layer {layer} weight gradient")
+    _within_acc_bound(db, gr.sum(axis=(0, 1)), np.abs(gr).sum(axis=(0, 1)), npos,
+                      f"layer {layer} bias gradient")

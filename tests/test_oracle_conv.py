@@ -160,3 +160,36 @@ def test_jump_inverts_target():
     r = np.array([0.7, 1.9])
     _, s = cr.features(u, r)
     np.testing.assert_allclose(cr.jump(u, cr.target(u, u64, r, s), r, s), u64, rtol=0, atol=1e-15)
+
+
+def test_bf16_forward_rounds_where_the_device_stores_bf16():
+    """forward(bf=True) rounds to bfloat16 exactly where the GPU network
+    keeps bfloat16 tensors -- the input features, each layer's weights, the
+    stored pre-activations and activations -- while the sums, the bias, the
+    GELU argument and the output stay unrounded: checked against the layer
+    sequence written out step by step, and the rounding points shown to
+    matter (moving one changes the result)."""
+    rng = np.random.default_rng(5)
+    params = [(w, 0.05 * rng.standard_normal(b.size)) for w, b in cr.init_params(5)]
+    u = rng.standard_normal((2, 128)).cumsum(axis=1)
+    x, _ = cr.features(u, np.array([0.7, 1.6]))
+    out, cache = cr.forward(params, x, bf=True)
+    h = cr.bf16(x)
+    for li, (w, b) in enumerate(params):
+        np.testing.assert_array_equal(cache["inputs"][li], h)
+        z = cr.conv(h, cr.bf16(w), cr.DILATIONS[li]) + b
+        if li == len(params) - 1:
+            np.testing.assert_array_equal(out, z[:, :, 0])
+            break
+        np.testing.assert_array_equal(cache["pre"][li], cr.bf16(z))
+        a = cr.gelu(z)
+        h = cr.bf16(h + a if li > 0 else a)
+    for t in cache["inputs"] + cache["pre"][:5]:
+        np.testing.assert_array_equal(t, cr.bf16(t))
+    # GELU of the rounded pre-activation would be another function
+    h0 = cr.bf16(x)
+    z0 = cr.conv(h0, cr.bf16(params[0][0]), 1) + params[0][1]
+    assert not np.array_equal(cr.bf16(cr.gelu(z0)), cr.bf16(cr.gelu(cr.bf16(z0))))
+    # and the rounded forward differs from the FP64 one
+    out64, _ = cr.forward(params, x, bf=False)
+    assert 1e-6 < np.linalg.norm(out - out64) / np.linalg.norm(out64) < 0.1

@@ -670,6 +670,10 @@ def main():
                 torch.cuda.synchronize()
                 wr, gr_ = time_runs(torch, stream, lambda: pl.step_n(uu, 0, LEVELS, workspace=wsp,
                                                                     stream=stream), 1, 3)
+            # parity: one more run from u0
+            with torch.cuda.stream(stream):
+                uu.copy_(ui)
+                pl.step_n(uu, 0, LEVELS, workspace=wsp, stream=stream)
             pl.check(stream)
             c2 = pl.config()
             lo = N2 // 2 - 32

@@ -2,7 +2,8 @@
 
     python -m paper_1310_3422_amd.runs batch [--precision fp32] [--levels 2000]
         the 4096-rod batch (N log-uniform in [256, 65536], r in [0.25, 4],
-        walls in [-1, 1], seed 3), one graph-captured solve
+        walls in [-1, 1], seed 3), one graph-captured solve (rods above the
+        form's on-chip limit run as long-rod tasks)
     python -m paper_1310_3422_amd.runs subdomain [--k 16] [--precision fp64] [--levels 960]
         the sub-domain scheme on a rod of 2^24 - 1 points (16-mode sine u0,
         seed 2, r = 2)
@@ -41,8 +42,7 @@ def _timed(torch, stream, fn):
 def batch(precision, levels):
     import torch
     from . import ge, inputs
-    rb = inputs.rod_batch(seed=3, nrods=4096, nmax=65536 if precision == "fp32" else 32768,
-                          align=4)
+    rb = inputs.rod_batch(seed=3, nrods=4096, align=4)
     b = ge.Batch.from_inputs(rb, precision)
     u = ge.pack_batch_state(rb.u0, rb.offsets, rb.n, precision)
     ws = b.new_workspace()

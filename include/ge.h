@@ -331,6 +331,22 @@ ge_status ge_batch_info(ge_batch_t batch, int32_t *ntasks, int32_t *grid,
 ge_status ge_solve_batch(ge_batch_t batch, void *u, void *workspace,
                          int64_t step0, int64_t nsteps, void *stream);
 
+/* ge_solve_batch for callers that cannot allocate device memory or
+ * instantiate a graph (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation): the same run, bit for bit, with the
+ * task queue head and the second level buffers of the rods above the
+ * on-chip limit in a static scratch array of the library (32 MiB per GPU,
+ * held from the first call on that GPU until the process ends), launched
+ * directly on `stream` (no graph).  It allocates nothing.  Every call on a
+ * GPU shares that GPU's scratch: calls that overlap on one GPU (on two
+ * streams, or from two threads) race and give undefined results.
+ * Errors: GE_ERR_INVALID (as ge_solve_batch), GE_ERR_UNSUPPORTED (the plan's
+ * rods above the on-chip limit need more than 32 MiB - 256 B of second
+ * level buffers, ge_batch_workspace_bytes() > 32 MiB), GE_ERR_SYNC /
+ * GE_ERR_NONFINITE (as ge_solve_batch), GE_ERR_HIP. */
+ge_status ge_solve_batch_static(ge_batch_t batch, void *u, int64_t step0, int64_t nsteps,
+                                void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned 64-level propagator (surrogate).  A 1D convolutional network over
  * the points of a rod maps u at level m to a normalised increment; a jump is

@@ -96,6 +96,12 @@ struct HaloLayout {
 
 hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream);
 
+// Library-owned scratch of the allocation-free entry point: a file-scope
+// device array of kBatchScratchBytes per GPU (the queue head at byte 0, the
+// long rods' second level buffers from byte 256).  batch_scratch returns its
+// device address on the current device, looked up once per device.
+constexpr size_t kBatchScratchBytes = (size_t)32 << 20;
+void *batch_scratch(hipError_t *err);
 int batch_max_k(int prec);
 
 }  // namespace ge

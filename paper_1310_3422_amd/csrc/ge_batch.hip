@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -590,8 +591,39 @@ __global__ __launch_bounds__(kThreads) void batch_kernel(BatchArgs a)
 
 __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
 
+// The allocation-free entry point's scratch (see batch_scratch).  Host code
+// never passes this name to a kernel: it is a host-side stand-in, and the
+// device address comes from hipGetSymbolAddress, per device.
+__device__ __align__(256) unsigned char scratch[kBatchScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+
 }  // namespace
 
+void *batch_scratch(hipError_t *err)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= kMaxDevices)) e = hipErrorInvalidDevice;
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *err = hipSuccess;
+    return g_scratch_addr[dev];
+}
 
 hipError_t launch_batch(int prec, const BatchArgs &a, int grid, hipStream_t stream)
 {

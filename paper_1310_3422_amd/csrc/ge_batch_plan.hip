@@ -777,3 +777,31 @@ ge_status ge_solve_batch(ge_batch_t b, void *u, void *workspace, int64_t step0, 
 }
 
 }  // extern "C"
+
+extern "C" {
+
+ge_status ge_solve_batch_static(ge_batch_t b, void *u, int64_t step0, int64_t nsteps,
+                                void *stream)
+{
+    {
+        const ge_status rs = check_run(b, u, step0, nsteps, "ge_solve_batch_static");
+        if (rs != GE_OK) return rs;
+    }
+    const size_t need = ge_batch_workspace_bytes(b);
+    if (need > ge::kBatchScratchBytes)
+        return fail(GE_ERR_UNSUPPORTED,
+                    "ge_solve_batch_static: the plan needs %zu bytes of scratch (its rods above "
+                    "the on-chip limit), the library's static scratch holds %zu",
+                    need, ge::kBatchScratchBytes);
+    if (nsteps == 0)
+        return GE_OK;
+    hipError_t e = hipSuccess;
+    void *work = ge::batch_scratch(&e);
+    if (!work)
+        return hip_fail(e, "ge_solve_batch_static: scratch address");
+    const ge::BatchArgs a = run_args(b, u, work, step0, nsteps);
+    e = ge::launch_batch(b->prec, a, b->grid, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GE_OK : hip_fail(e, "ge_solve_batch_static: launch");
+}
+
+}  // extern "C"

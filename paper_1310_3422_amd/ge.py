@@ -73,6 +73,7 @@ _SIGS = {
                                      ctypes.POINTER(_dbl), _vp]),
     "ge_solve_batch": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
     "ge_batch_set_wait_polls": (ctypes.c_int, [_vp, _i64]),
+    "ge_solve_batch_static": (ctypes.c_int, [_vp, _vp, _i64, _i64, _vp]),
     "ge_batch_check": (ctypes.c_int, [_vp, _vp]),
     "ge_plan_schedule": (_i32, [_vp]),
     "ge_nn_param_count": (_i64, []),
@@ -333,6 +334,14 @@ class Batch:
             raise ValueError("workspace too small")
         check(lib().ge_solve_batch(self.handle, _ptr(u), _ptr(workspace), int(step0),
                                    int(nsteps), _stream_ptr(stream)))
+        return u
+
+    def solve_static(self, u, step0, nsteps, stream=None):
+        """ge_solve_batch_static: the same run with the library's static
+        scratch (allocates nothing, no graph)."""
+        Plan._check_tensor(u, self.state_elems, "u", state_dtype(self.precision))
+        check(lib().ge_solve_batch_static(self.handle, _ptr(u), int(step0), int(nsteps),
+                                          _stream_ptr(stream)))
         return u
 
     def set_wait_polls(self, polls):

@@ -317,8 +317,9 @@ def surrogate_extra(torch, stream, train_steps, nrods=4096, width=4096, ntraj=20
     from paper_1310_3422_amd import ge, surrogate, inputs
     t0 = time.perf_counter()
     net = ge.Net(width=width, max_batch=nrods, seed=4)
-    tr, log = surrogate.train_recipe(net, train_steps, seed=4, ntraj=ntraj, minibatch=64,
-                                     log_every=max(train_steps // 8, 1))
+    tr, log = surrogate.train_recipe(
+        net, train_steps, seed=4, ntraj=ntraj, minibatch=64, log_every=max(train_steps // 8, 1),
+        progress=lambda m: print(f"[bench] surrogate: {m}", file=sys.stderr, flush=True))
     del tr
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0      # trajectory generation included
@@ -398,7 +399,8 @@ def kernel_name(prec, cfg, src):
     form = "comp" if prec == "fp32c" else "plain"
     if cfg["schedule"] == 2:
         return f"tile_persistent_kernel<{t},{cfg['tile']},{form},{'src' if src else 'nosrc'}>"
-    return f"tile_kernel<{t},{cfg['tile']},{cfg['waves']},{form},{'src' if src else 'nosrc'}>"
+    return (f"tile_kernel<{t},{cfg['tile']},{cfg['waves']},{form},{'src' if src else 'nosrc'},"
+            "interior>")
 
 
 def roofline_of(prec, cfg, n, levels, steps, gpu_s, src, traffic=None):
@@ -424,7 +426,10 @@ def roofline_of(prec, cfg, n, levels, steps, gpu_s, src, traffic=None):
         "bound": "alu", "achieved": round(ach, 2), "peak": PEAK_TF[prec], "unit": "TFLOP/s",
         "frac": round(ach / PEAK_TF[prec], 4), "traffic": traffic,
         "kernel": kernel_name(prec, cfg, src), "depth": cfg["depth"], "launches": nl,
-        "avg_launch_us": round(kernel_s * 1e6, 2), "flops_per_update": fpu,
+        "avg_launch_us": round(kernel_s * 1e6, 2),
+        "avg_launch_basis": "per block of levels: the interior-tile kernel, the wall-tile "
+                            "kernel before it and the gaps (HIP events)",
+        "flops_per_update": fpu,
         "algorithmic_flops_per_launch": flops,
         "issue_floor": {"peak": round(floor, 2), "frac": round(ach / floor, 4),
                         "basis": f"VALU issue {VALU_LANE_OPS_BY_PREC[prec]:.3g} lane-ops/s x "

@@ -123,9 +123,13 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // source and of 2^27 points with moving walls and a source.  At a few levels
 // per launch the sweep streams HBM, and narrow per-lane rows (one or two
 // 16-byte chunks) coalesce best; deep launches are issue-bound and want wide
-// rows, few halo points and no workgroup barrier.  With a source profile the
-// persistent schedule's second register copy of the profile costs more than
-// its prefetch gains, so those rods stay on one workgroup per tile.
+// rows, few halo points and no workgroup barrier.  With a source the
+// interior tiles hold two per-parity weight arrays besides the state, so
+// the persistent schedule's prefetch registers cost more occupancy than the
+// prefetch gains, and those rods stay on one workgroup per tile: FP64 at 16
+// points per lane (142 registers, three waves per SIMD; 32 points need
+// more than the register file), FP32 at 32 (64 levels: 7.7e12 updates/s
+// against 7.4e12 at 16).
 struct Choice {
     int tile, waves, depth;
 };
@@ -138,11 +142,12 @@ Choice default_choice(int prec, int depth, bool src)
         return {depth <= 64 ? 8 : 16, 4, depth};
     }
     const bool f64 = prec == ge::kFP64;
-    if (depth == 0) return src ? Choice{16, 1, 64} : Choice{32, 1, 96};
+    if (depth == 0) return src ? Choice{f64 ? 16 : 32, 1, 64} : Choice{32, 1, 96};
     if (depth <= 4) return {f64 ? 2 : 4, 1, depth};
     if (depth <= 8) return {(f64 || !src) ? (f64 ? 4 : 8) : 4, 1, depth};
     if (depth <= 16) return {f64 ? (src ? 4 : 8) : 16, 1, depth};
-    if (depth <= 32 || src) return {16, 1, depth};
+    if (src) return {f64 ? 16 : 32, 1, depth};
+    if (depth <= 32) return {16, 1, depth};
     return {32, 1, depth};
 }
 

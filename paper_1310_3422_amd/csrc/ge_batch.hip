@@ -190,9 +190,10 @@ __device__ __forceinline__ void run_task(const BatchArgs &a, const BatchTask &tk
             rod_levels<T, K, COMP, false, NBR>(a, rd, wr, hasR, s, e, xs, xe, lvl);
     }
     if (rod >= 0) {
-        check_finite<T, K, COMP>(a.status, s, e, g0, 0, rd.n);
-        store_lane_upto<T, K>(us + g0, g0, rd.n, s);
-        if constexpr (COMP) store_lane_upto<T, K>(ue + g0, g0, rd.n, e);
+        T fin = T(0);
+        store_lane_upto<T, K>(us + g0, g0, rd.n, s, fin);
+        if constexpr (COMP) store_lane_upto<T, K>(ue + g0, g0, rd.n, e, fin);
+        raise_if_nonfinite(a.status, fin);
     }
     __syncthreads();   // LDS slots are reused by the next task
 }
@@ -471,14 +472,12 @@ __device__ __forceinline__ void run_task_halo(const BatchArgs &a, const BatchTas
     }
     // lanes 1..62, lane 0 of the first wave and lane 63 of the last (the last
     // wave from its neighbour's core end on)
-    if (rod >= 0) {
-        const bool mine = (lane > 0 || wr == 0) && (lane < kWave - 1 || !hasR);
-        check_finite<T, K, COMP>(a.status, s, e, g0, mine ? lo : rd.n, rd.n);
-    }
+    T fin = T(0);
     if (rod >= 0 && (lane > 0 || wr == 0) && (lane < kWave - 1 || !hasR)) {
-        store_lane_range<T, K>(us + g0, g0, lo, rd.n, s);
-        if constexpr (COMP) store_lane_range<T, K>(ue + g0, g0, lo, rd.n, e);
+        store_lane_range<T, K>(us + g0, g0, lo, rd.n, s, fin);
+        if constexpr (COMP) store_lane_range<T, K>(ue + g0, g0, lo, rd.n, e, fin);
     }
+    if (rod >= 0) raise_if_nonfinite(a.status, fin);
     __syncthreads();   // LDS slots are reused by the next task
 }
 

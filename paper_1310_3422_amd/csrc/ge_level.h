@@ -121,6 +121,36 @@ __device__ __forceinline__ T edge_right(T fill, T v)
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Raise a status word (StatusWord, ge_kernels.h): host-mapped memory of the
+// plan, written with a plain system-scope store, so no read-modify-write
+// crosses the bus.
+__device__ __forceinline__ void raise_status(int *status, int word)
+{
+    __hip_atomic_store(status + word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// The stored values are tested as they are stored: acc + v * 0 over them
+// stays 0 while they are finite and becomes NaN once one is NaN or infinite
+// (one FMA per value, no compare).  Values a lane holds but does not store
+// (halo points, points past a wall) are not tested: past a wall they are
+// not part of the problem and may grow without bound.
+template <typename T>
+__device__ __forceinline__ void finite_acc(T &acc, T v)
+{
+    acc = fmaT(v, T(0), acc);
+}
+
+// Raise kStatusNonfinite if some lane's stored values were not all finite;
+// at most one store per wave.  Called by every lane of the wave.
+template <typename T>
+__device__ __forceinline__ void raise_if_nonfinite(int *status, T acc)
+{
+    if (!status) return;
+    const uint64_t m = __ballot(!__builtin_isfinite(acc));
+    if (m != 0 && (threadIdx.x & (kWave - 1)) == (unsigned)__builtin_ctzll(m))
+        raise_status(status, kStatusNonfinite);
+}
+
 // ---- 16-byte vector access to a lane's K contiguous values ----------------
 template <typename T> struct V16;
 template <> struct V16<float> { using type = float4; static constexpr int E = 4; };
@@ -172,7 +202,7 @@ __device__ __forceinline__ void load_lane_guarded(const T *__restrict__ p, int64
 // multiples of the chunk width on the fast path.
 template <typename T, int K>
 __device__ __forceinline__ void store_lane_chunks(T *__restrict__ p, int64_t g0, int64_t lo,
-                                                  int64_t hi, const T (&v)[K])
+                                                  int64_t hi, const T (&v)[K], T &fin)
 {
     using V = typename V16<T>::type;
     constexpr int E = V16<T>::E;
@@ -181,6 +211,8 @@ __device__ __forceinline__ void store_lane_chunks(T *__restrict__ p, int64_t g0,
     for (int c = 0; c < K / E; ++c) {
         const int64_t g = g0 + c * E;
         if (g >= lo && g < hi) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) finite_acc(fin, v[c * E + i]);
             V x;
             if constexpr (E == 4) {
                 x.x = v[4 * c]; x.y = v[4 * c + 1]; x.z = v[4 * c + 2]; x.w = v[4 * c + 3];
@@ -194,19 +226,21 @@ __device__ __forceinline__ void store_lane_chunks(T *__restrict__ p, int64_t g0,
 
 template <typename T, int K>
 __device__ __forceinline__ void store_lane_guarded(T *__restrict__ p, int64_t g0, int64_t lo,
-                                                   int64_t hi, const T (&v)[K])
+                                                   int64_t hi, const T (&v)[K], T &fin)
 {
 #pragma unroll
     for (int j = 0; j < K; ++j)
-        if (g0 + j >= lo && g0 + j < hi)
+        if (g0 + j >= lo && g0 + j < hi) {
+            finite_acc(fin, v[j]);
             p[j] = v[j];
+        }
 }
 
 // Store the values whose global index is below n: whole 16-byte chunks
 // where they lie below n, single values in the chunk that straddles n.
 template <typename T, int K>
 __device__ __forceinline__ void store_lane_upto(T *__restrict__ p, int64_t g0, int64_t n,
-                                                const T (&v)[K])
+                                                const T (&v)[K], T &fin)
 {
     using V = typename V16<T>::type;
     constexpr int E = V16<T>::E;
@@ -214,6 +248,8 @@ __device__ __forceinline__ void store_lane_upto(T *__restrict__ p, int64_t g0, i
 #pragma unroll
     for (int c = 0; c < K / E; ++c) {
         if (g0 + (c + 1) * E <= n) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) finite_acc(fin, v[c * E + i]);
             V x;
             if constexpr (E == 4) {
                 x.x = v[4 * c]; x.y = v[4 * c + 1]; x.z = v[4 * c + 2]; x.w = v[4 * c + 3];
@@ -224,8 +260,10 @@ __device__ __forceinline__ void store_lane_upto(T *__restrict__ p, int64_t g0, i
         } else {
 #pragma unroll
             for (int i = 0; i < E; ++i)
-                if (g0 + c * E + i < n)
+                if (g0 + c * E + i < n) {
+                    finite_acc(fin, v[c * E + i]);
                     p[c * E + i] = v[c * E + i];
+                }
         }
     }
 }
@@ -235,7 +273,7 @@ __device__ __forceinline__ void store_lane_upto(T *__restrict__ p, int64_t g0, i
 // straddles n goes value by value.
 template <typename T, int K>
 __device__ __forceinline__ void store_lane_range(T *__restrict__ p, int64_t g0, int64_t lo,
-                                                 int64_t n, const T (&v)[K])
+                                                 int64_t n, const T (&v)[K], T &fin)
 {
     using V = typename V16<T>::type;
     constexpr int E = V16<T>::E;
@@ -245,6 +283,8 @@ __device__ __forceinline__ void store_lane_range(T *__restrict__ p, int64_t g0, 
         if (g0 + c * E < lo)
             continue;
         if (g0 + (c + 1) * E <= n) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) finite_acc(fin, v[c * E + i]);
             V x;
             if constexpr (E == 4) {
                 x.x = v[4 * c]; x.y = v[4 * c + 1]; x.z = v[4 * c + 2]; x.w = v[4 * c + 3];
@@ -255,8 +295,10 @@ __device__ __forceinline__ void store_lane_range(T *__restrict__ p, int64_t g0, 
         } else {
 #pragma unroll
             for (int i = 0; i < E; ++i)
-                if (g0 + c * E + i < n)
+                if (g0 + c * E + i < n) {
+                    finite_acc(fin, v[c * E + i]);
                     p[c * E + i] = v[c * E + i];
+                }
         }
     }
 }
@@ -303,34 +345,6 @@ __device__ __forceinline__ T get_at(const T (&v)[K], int k, T otherwise)
     return r;
 }
 
-// Raise a status word (StatusWord, ge_kernels.h): host-mapped memory of the
-// plan, written with a plain system-scope store, so no read-modify-write
-// crosses the bus.
-__device__ __forceinline__ void raise_status(int *status, int word)
-{
-    __hip_atomic_store(status + word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
-// Raise kStatusNonfinite when a value of the lane with global index in
-// [lo, hi) (the values the caller is about to store) is NaN or infinite.
-// One class test per value; at most one store per wave.
-template <typename T, int K, bool COMP>
-__device__ __forceinline__ void check_finite(int *status, const T (&s)[K], const T (&e)[K],
-                                             int64_t g0, int64_t lo, int64_t hi)
-{
-    if (!status) return;
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const bool in = g0 + j >= lo && g0 + j < hi;
-        bool nf = !__builtin_isfinite(s[j]);
-        if constexpr (COMP) nf = nf || !__builtin_isfinite(e[j]);
-        bad = bad || (in && nf);
-    }
-    const uint64_t m = __ballot(bad);
-    if (m != 0 && (threadIdx.x & (kWave - 1)) == (unsigned)__builtin_ctzll(m))
-        raise_status(status, kStatusNonfinite);
-}
 
 // A first difference: one value, or the (s, e) parts of the pair kept apart.
 template <typename T, bool COMP> struct Dif { T s; };

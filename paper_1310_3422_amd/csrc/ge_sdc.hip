@@ -216,7 +216,7 @@ __device__ __forceinline__ void stage_load(const T *__restrict__ in, int64_t bas
 // lie below n (lo, hi multiples of K)
 template <typename T, int K>
 __device__ __forceinline__ void stage_store(T *__restrict__ out, int64_t base, int64_t n, int lo,
-                                            int hi, T *lds, const T (&s)[K])
+                                            int hi, T *lds, const T (&s)[K], T &fin)
 {
     using S = Stage<T, K>;
     using V = typename V16<T>::type;
@@ -238,18 +238,23 @@ __device__ __forceinline__ void stage_store(T *__restrict__ out, int64_t base, i
             continue;
         const int64_t g = base + e0;
         const V x = *reinterpret_cast<const V *>(&lds[(e0 / K) * S::P + e0 % K]);
+        T u[S::E];
+        if constexpr (S::E == 4) {
+            u[0] = x.x; u[1] = x.y; u[2] = x.z; u[3] = x.w;
+        } else {
+            u[0] = x.x; u[1] = x.y;
+        }
         if (g + S::E <= n) {
+#pragma unroll
+            for (int q = 0; q < S::E; ++q) finite_acc(fin, u[q]);
             *reinterpret_cast<V *>(out + g) = x;
         } else {
-            T u[S::E];
-            if constexpr (S::E == 4) {
-                u[0] = x.x; u[1] = x.y; u[2] = x.z; u[3] = x.w;
-            } else {
-                u[0] = x.x; u[1] = x.y;
-            }
 #pragma unroll
             for (int q = 0; q < S::E; ++q)
-                if (g + q < n) out[g + q] = u[q];
+                if (g + q < n) {
+                    finite_acc(fin, u[q]);
+                    out[g + q] = u[q];
+                }
         }
     }
 }
@@ -282,8 +287,9 @@ __global__ __launch_bounds__(kWave) void sdc_tile_kernel(TileArgs a)
                                          (T)gr(lev + 1));
     });
     const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
-    check_finite<T, K, false>(a.status, s, s, i * K, c0 * K, c1 * K < a.n ? c1 * K : a.n);
-    stage_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds, s);
+    T fin = T(0);
+    stage_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds, s, fin);
+    raise_if_nonfinite(a.status, fin);
 }
 
 // Persistent form.  Single-wave workgroups stay resident and take the tiles
@@ -402,7 +408,7 @@ __device__ __forceinline__ void rows_swap(T *lds, T (&s)[K])
 // values of window positions [lo, hi) below n, from the buffer to `out`
 template <typename T, int K>
 __device__ __forceinline__ void chunks_store(T *__restrict__ out, int64_t base, int64_t n, int lo,
-                                             int hi, const T *lds)
+                                             int hi, const T *lds, T &fin)
 {
     using S = Swz<T, K>;
     using V = typename V16<T>::type;
@@ -415,14 +421,19 @@ __device__ __forceinline__ void chunks_store(T *__restrict__ out, int64_t base, 
             continue;
         const int64_t g = base + e0;
         const V x = *reinterpret_cast<const V *>(&lds[sl * S::E]);
+        T u[K];
+        unpack<T, K>(x, u, 0);
         if (g + S::E <= n) {
+#pragma unroll
+            for (int q = 0; q < S::E; ++q) finite_acc(fin, u[q]);
             *reinterpret_cast<V *>(out + g) = x;
         } else {
-            T u[K];
-            unpack<T, K>(x, u, 0);
 #pragma unroll
             for (int q = 0; q < S::E; ++q)
-                if (g + q < n) out[g + q] = u[q];
+                if (g + q < n) {
+                    finite_acc(fin, u[q]);
+                    out[g + q] = u[q];
+                }
         }
     }
 }
@@ -496,7 +507,6 @@ __global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int n
         });
         const int64_t c0 = t * a.core;
         const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
-        check_finite<T, K, false>(a.status, s, s, i * K, c0 * K, c1 * K < a.n ? c1 * K : a.n);
         if (more) {
             wait_vmem();
             tail_fix<T, K>(in, wstart(tn) * K, a.n, lds);
@@ -504,7 +514,9 @@ __global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int n
         } else {
             rows_write<T, K>(lds, s);
         }
-        chunks_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds);
+        T fin = T(0);
+        chunks_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds, fin);
+        raise_if_nonfinite(a.status, fin);
         if (!more)
             break;
         t = tn;

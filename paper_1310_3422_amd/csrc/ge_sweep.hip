@@ -18,24 +18,6 @@ namespace {
 
 using namespace dev;
 
-template <typename T, int K, int NW, bool COMP, bool SRC>
-__global__ __launch_bounds__(NW *kWave) void tile_kernel(TileArgs a)
-{
-    // Consecutive tiles go to the same XCD (workgroups are dealt to the 8
-    // XCDs round-robin), so neighbouring halos share that XCD's L2.
-    const int64_t per = gridDim.x / 8;
-    const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (t >= a.ntiles)
-        return;
-    const int64_t ws = (t == 0) ? 0 : t * a.core - a.halo;
-    constexpr int64_t W = NW * kWave * K;
-    const bool wall = (ws == 0) || (ws + W >= a.n);
-    if (wall)
-        run_tile<T, K, NW, COMP, SRC, true>(a, threadIdx.x, t, ws);
-    else
-        run_tile<T, K, NW, COMP, SRC, false>(a, threadIdx.x, t, ws);
-}
-
 // First tile whose window reaches the right wall (tiles from there on, and
 // tile 0, take the wall path).
 __device__ __host__ inline int64_t first_right_wall_tile(const TileArgs &a, int64_t W)
@@ -46,23 +28,57 @@ __device__ __host__ inline int64_t first_right_wall_tile(const TileArgs &a, int6
     return t < a.ntiles ? t : a.ntiles;
 }
 
-// Persistent form for single-wave windows.  The first nint workgroups sweep
-// the interior tiles round-robin, each loading its next tile while the
-// current one advances, so the loads hide behind the levels; the remaining
-// workgroups take one wall tile each.  Consecutive interior tiles are dealt
-// to the same XCD, as in tile_kernel.
+// The tiles of a launch.  PART 0: every tile, each taking the wall path or
+// not.  The wall path (guarded loads, runtime wall positions, the flux, the
+// source profile kept for the lone points) needs far more registers than an
+// interior tile, and a kernel holds the registers of its widest path in
+// every wave; so rods of several tiles run two kernels per launch: PART 2
+// takes tile 0 and the tiles reaching the right wall (one workgroup each),
+// PART 1 the interior tiles 1 .. tw-1 at the interior path's occupancy.
+template <typename T, int K, int NW, bool COMP, bool SRC, int PART>
+__global__ __launch_bounds__(NW *kWave) void tile_kernel(TileArgs a)
+{
+    constexpr int64_t W = NW * kWave * K;
+    if constexpr (PART == 2) {
+        const int64_t tw = first_right_wall_tile(a, W);
+        const int64_t t = blockIdx.x == 0 ? 0 : tw + blockIdx.x - 1;
+        if (t < a.ntiles)
+            run_tile<T, K, NW, COMP, SRC, true>(a, threadIdx.x, t, t == 0 ? 0 : t * a.core - a.halo);
+        return;
+    }
+    // Consecutive tiles go to the same XCD (workgroups are dealt to the 8
+    // XCDs round-robin), so neighbouring halos share that XCD's L2.
+    const int64_t per = gridDim.x / 8;
+    const int64_t i = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if constexpr (PART == 1) {
+        const int64_t t = 1 + i;
+        if (t < first_right_wall_tile(a, W))
+            run_tile<T, K, NW, COMP, SRC, false>(a, threadIdx.x, t, t * a.core - a.halo);
+        return;
+    }
+    const int64_t t = i;
+    if (t >= a.ntiles)
+        return;
+    const int64_t ws = (t == 0) ? 0 : t * a.core - a.halo;
+    const bool wall = (ws == 0) || (ws + W >= a.n);
+    if (wall)
+        run_tile<T, K, NW, COMP, SRC, true>(a, threadIdx.x, t, ws);
+    else
+        run_tile<T, K, NW, COMP, SRC, false>(a, threadIdx.x, t, ws);
+}
+
+// Persistent form for single-wave windows: nint workgroups sweep the
+// interior tiles round-robin, each loading its next tile while the current
+// one advances, so the loads hide behind the levels.  Consecutive interior
+// tiles are dealt to the same XCD, as in tile_kernel.  The wall tiles run in
+// a separate launch (tile_kernel, PART 2), so this kernel holds only the
+// interior path's registers.
 template <typename T, int K, bool COMP, bool SRC>
 __global__ __launch_bounds__(kWave) void tile_persistent_kernel(TileArgs a, int nint)
 {
     constexpr int64_t W = kWave * K;
     const int64_t tw = first_right_wall_tile(a, W);
     const int g = blockIdx.x;
-    if (g >= nint) {
-        const int64_t t = g == nint ? 0 : tw + (g - nint - 1);
-        if (t < a.ntiles && (t == 0 || t >= tw))
-            run_tile<T, K, 1, COMP, SRC, true>(a, threadIdx.x, t, t == 0 ? 0 : t * a.core - a.halo);
-        return;
-    }
     const int per = nint / 8;
     const int gx = (g % 8) * per + g / 8;        // XCD-aware order (nint is a multiple of 8)
     int64_t t = 1 + gx;
@@ -109,13 +125,18 @@ hipError_t launch_persistent(const TileArgs &a, hipStream_t stream)
     const int64_t tw = first_right_wall_tile(a, W);
     const int64_t interior = tw - 1;
     const int64_t walls = 1 + (a.ntiles - tw);
+    hipLaunchKernelGGL((tile_kernel<T, K, 1, COMP, SRC, 2>), dim3((unsigned)walls), dim3(kWave), 0,
+                       stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || interior < 1)
+        return e;
     // as many workgroups as stay resident, trimmed so that every one gets
     // the same number of tiles (to one), in multiples of 8
     const int64_t cap = (int64_t)per_cu * ncu;
     const int64_t rounds = (interior + cap - 1) / cap;
     int64_t nint = (interior + rounds - 1) / rounds;
     nint = (nint + 7) / 8 * 8;
-    hipLaunchKernelGGL((tile_persistent_kernel<T, K, COMP, SRC>), dim3((unsigned)(nint + walls)),
+    hipLaunchKernelGGL((tile_persistent_kernel<T, K, COMP, SRC>), dim3((unsigned)nint),
                        dim3(kWave), 0, stream, a, (int)nint);
     return hipGetLastError();
 }
@@ -123,8 +144,23 @@ hipError_t launch_persistent(const TileArgs &a, hipStream_t stream)
 template <typename T, int K, int NW, bool COMP, bool SRC>
 hipError_t launch_one(const TileArgs &a, hipStream_t stream)
 {
-    const int64_t grid = (a.ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((tile_kernel<T, K, NW, COMP, SRC>), dim3((unsigned)grid),
+    constexpr int64_t W = NW * kWave * K;
+    const int64_t tw = a.ntiles >= 3 ? first_right_wall_tile(a, W) : 1;
+    if (tw < 2) {
+        // no interior tile: every tile in one launch
+        const int64_t grid = (a.ntiles + 7) / 8 * 8;
+        hipLaunchKernelGGL((tile_kernel<T, K, NW, COMP, SRC, 0>), dim3((unsigned)grid),
+                           dim3(NW * kWave), 0, stream, a);
+        return hipGetLastError();
+    }
+    const int64_t walls = 1 + (a.ntiles - tw);
+    hipLaunchKernelGGL((tile_kernel<T, K, NW, COMP, SRC, 2>), dim3((unsigned)walls),
+                       dim3(NW * kWave), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    const int64_t grid = (tw - 1 + 7) / 8 * 8;
+    hipLaunchKernelGGL((tile_kernel<T, K, NW, COMP, SRC, 1>), dim3((unsigned)grid),
                        dim3(NW * kWave), 0, stream, a);
     return hipGetLastError();
 }

@@ -202,14 +202,15 @@ __device__ __forceinline__ void sweep_tile(const TileArgs &a, int tid, int64_t t
     if (own_L && tid == 0) a.flux[0] = accL;
     if (own_R && tid == lS) a.flux[1] = accR;
 
-    check_finite<T, K, COMP>(a.status, s, e, g0, core_lo, core_hi);
+    T fin = T(0);
     if constexpr (WALL) {
-        store_lane_guarded<T, K>(out_s + g0, g0, core_lo, core_hi, s);
-        if constexpr (COMP) store_lane_guarded<T, K>(out_e + g0, g0, core_lo, core_hi, e);
+        store_lane_guarded<T, K>(out_s + g0, g0, core_lo, core_hi, s, fin);
+        if constexpr (COMP) store_lane_guarded<T, K>(out_e + g0, g0, core_lo, core_hi, e, fin);
     } else {
-        store_lane_chunks<T, K>(out_s + g0, g0, core_lo, core_hi, s);
-        if constexpr (COMP) store_lane_chunks<T, K>(out_e + g0, g0, core_lo, core_hi, e);
+        store_lane_chunks<T, K>(out_s + g0, g0, core_lo, core_hi, s, fin);
+        if constexpr (COMP) store_lane_chunks<T, K>(out_e + g0, g0, core_lo, core_hi, e, fin);
     }
+    raise_if_nonfinite(a.status, fin);
 }
 
 template <typename T, int K, int NW, bool COMP, bool SRC, bool WALL>

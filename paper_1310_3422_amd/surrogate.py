@@ -92,8 +92,9 @@ class Trainer:
     training and sampled for a share of the minibatches."""
 
     def __init__(self, net, seed=4, ntraj=2048, chunk=1024, njumps=8, minibatch=64,
-                 noise=None, modes=None):
+                 noise=None, modes=None, progress=None):
         self.net = net
+        self.progress = progress
         self.seed, self.ntraj, self.chunk = seed, ntraj, min(chunk, ntraj)
         self.njumps, self.minibatch = njumps, minibatch
         self.rng = np.random.default_rng([seed, 1 << 20])
@@ -102,6 +103,8 @@ class Trainer:
             nr = min(self.chunk, ntraj - c * self.chunk)
             self.chunks.append(Trajectories([seed, c], nr, net.width, njumps, noise=noise,
                                             modes=modes))
+            if progress and (c + 1) % 32 == 0:
+                progress(f"{(c + 1) * self.chunk} trajectories generated")
         torch = _torch()
         B, W = minibatch, net.width
         self.u = torch.empty(B * W, dtype=torch.float32, device="cuda")
@@ -155,6 +158,8 @@ class Trainer:
             self.steps += 1
             if log_every and (i % log_every == 0 or i == steps - 1):
                 out.append((self.steps, float(self.loss.cpu()[0])))
+                if self.progress:
+                    self.progress(f"step {self.steps}: loss {out[-1][1]:.3e}")
         return out
 
 
@@ -172,12 +177,12 @@ TRAIN_TRAJECTORIES = 200_000
 
 
 def train_recipe(net, steps, seed=4, ntraj=TRAIN_TRAJECTORIES, minibatch=64, lr=2e-3,
-                 lr_final=5e-5, log_every=0):
+                 lr_final=5e-5, log_every=0, progress=None):
     """Generate the recipe's trajectories with the batch sweep and train
     ``steps`` Adam steps, the second half with self-rollout sets refreshed
     12 times and drawn for half the minibatches; returns (trainer, loss log)."""
     tr = Trainer(net, seed=seed, ntraj=ntraj, chunk=min(1024, ntraj), njumps=8,
-                 minibatch=minibatch, noise=TRAIN_NOISE, modes=TRAIN_MODES)
+                 minibatch=minibatch, noise=TRAIN_NOISE, modes=TRAIN_MODES, progress=progress)
     log = tr.train(steps, lr=lr, lr_final=lr_final, log_every=log_every,
                    self_start=steps // 2, self_every=max(steps // 24, 1), self_share=0.5)
     return tr, log

@@ -32,9 +32,11 @@ __device__ __host__ inline int64_t first_right_wall_tile(const TileArgs &a, int6
 // not.  The wall path (guarded loads, runtime wall positions, the flux, the
 // source profile kept for the lone points) needs far more registers than an
 // interior tile, and a kernel holds the registers of its widest path in
-// every wave; so rods of several tiles run two kernels per launch: PART 2
+// every wave; so rods of very many tiles run two kernels per launch: PART 2
 // takes tile 0 and the tiles reaching the right wall (one workgroup each),
-// PART 1 the interior tiles 1 .. tw-1 at the interior path's occupancy.
+// PART 1 the interior tiles 1 .. tw-1 at the interior path's occupancy.  The
+// wall kernel runs before the interior one and costs about one tile's time,
+// which pays only when a CU sweeps hundreds of tiles per launch.
 template <typename T, int K, int NW, bool COMP, bool SRC, int PART>
 __global__ __launch_bounds__(NW *kWave) void tile_kernel(TileArgs a)
 {
@@ -67,18 +69,25 @@ __global__ __launch_bounds__(NW *kWave) void tile_kernel(TileArgs a)
         run_tile<T, K, NW, COMP, SRC, false>(a, threadIdx.x, t, ws);
 }
 
-// Persistent form for single-wave windows: nint workgroups sweep the
-// interior tiles round-robin, each loading its next tile while the current
-// one advances, so the loads hide behind the levels.  Consecutive interior
-// tiles are dealt to the same XCD, as in tile_kernel.  The wall tiles run in
-// a separate launch (tile_kernel, PART 2), so this kernel holds only the
-// interior path's registers.
+// Persistent form for single-wave windows.  The first nint workgroups sweep
+// the interior tiles round-robin, each loading its next tile while the
+// current one advances, so the loads hide behind the levels; the remaining
+// workgroups take one wall tile each, concurrently (a workgroup sweeps about
+// ten tiles per launch here, so a separate wall launch would cost about a
+// tenth; the prefetch registers exceed the wall path's anyway).
+// Consecutive interior tiles are dealt to the same XCD, as in tile_kernel.
 template <typename T, int K, bool COMP, bool SRC>
 __global__ __launch_bounds__(kWave) void tile_persistent_kernel(TileArgs a, int nint)
 {
     constexpr int64_t W = kWave * K;
     const int64_t tw = first_right_wall_tile(a, W);
     const int g = blockIdx.x;
+    if (g >= nint) {
+        const int64_t t = g == nint ? 0 : tw + (g - nint - 1);
+        if (t < a.ntiles && (t == 0 || t >= tw))
+            run_tile<T, K, 1, COMP, SRC, true>(a, threadIdx.x, t, t == 0 ? 0 : t * a.core - a.halo);
+        return;
+    }
     const int per = nint / 8;
     const int gx = (g % 8) * per + g / 8;        // XCD-aware order (nint is a multiple of 8)
     int64_t t = 1 + gx;
@@ -125,18 +134,13 @@ hipError_t launch_persistent(const TileArgs &a, hipStream_t stream)
     const int64_t tw = first_right_wall_tile(a, W);
     const int64_t interior = tw - 1;
     const int64_t walls = 1 + (a.ntiles - tw);
-    hipLaunchKernelGGL((tile_kernel<T, K, 1, COMP, SRC, 2>), dim3((unsigned)walls), dim3(kWave), 0,
-                       stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || interior < 1)
-        return e;
     // as many workgroups as stay resident, trimmed so that every one gets
     // the same number of tiles (to one), in multiples of 8
     const int64_t cap = (int64_t)per_cu * ncu;
-    const int64_t rounds = (interior + cap - 1) / cap;
-    int64_t nint = (interior + rounds - 1) / rounds;
+    const int64_t rounds = interior < 1 ? 1 : (interior + cap - 1) / cap;
+    int64_t nint = interior < 1 ? 0 : (interior + rounds - 1) / rounds;
     nint = (nint + 7) / 8 * 8;
-    hipLaunchKernelGGL((tile_persistent_kernel<T, K, COMP, SRC>), dim3((unsigned)nint),
+    hipLaunchKernelGGL((tile_persistent_kernel<T, K, COMP, SRC>), dim3((unsigned)(nint + walls)),
                        dim3(kWave), 0, stream, a, (int)nint);
     return hipGetLastError();
 }
@@ -145,8 +149,17 @@ template <typename T, int K, int NW, bool COMP, bool SRC>
 hipError_t launch_one(const TileArgs &a, hipStream_t stream)
 {
     constexpr int64_t W = NW * kWave * K;
+    // compute units (split launches only where a CU sweeps 128 tiles or more)
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu < 1)
+            ncu = 256;
+    }
     const int64_t tw = a.ntiles >= 3 ? first_right_wall_tile(a, W) : 1;
-    if (tw < 2) {
+    if (tw - 1 < 128 * (int64_t)ncu) {
         // no interior tile: every tile in one launch
         const int64_t grid = (a.ntiles + 7) / 8 * 8;
         hipLaunchKernelGGL((tile_kernel<T, K, NW, COMP, SRC, 0>), dim3((unsigned)grid),

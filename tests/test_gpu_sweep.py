@@ -305,3 +305,22 @@ def test_persistent_schedule_fp64_parity():
                   schedule=2)
     want = oracle.step_n(u0, 2.0, s, gl=0.5, gr=-0.25)
     assert rel_l2(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32c"])
+def test_split_wall_launch_is_bitwise_the_single_launch(precision):
+    """Launches of very many tiles (here more than 128 per CU: 2^23 points at
+    2 or 4 points per lane, one level per launch) run the wall tiles and the
+    interior tiles as two kernels; a plan of few large tiles runs one.  Same
+    bits, with moving walls, a source and the flux."""
+    n, s = (1 << 23) + 5, 7
+    w = inputs.moving_wall_rod(n, r=3.0, nsteps=s, step0=3)
+    u0 = inputs.sine_rod(n, 7) + 0.05 * np.random.default_rng(7).standard_normal(n)
+    tile = 2 if precision == "fp64" else 4
+    runs = []
+    for cfg in (dict(tile=tile, waves=1, depth=1, schedule=1),
+                dict(tile=16, waves=4, depth=s, schedule=1)):
+        runs.append(run_gpu(u0, 3.0, s, precision, step0=3, gl=w.g_left, gr=0.2, src_b=w.src_b,
+                            src_a=w.src_a, flux=True, **cfg))
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])

@@ -120,13 +120,18 @@ __device__ __forceinline__ void layer_mfma(const bf16 *act, const bf16 *ws, int 
     }
 }
 
-// The six-layer epilogue of a GELU layer for the wave's M-tiles: bias,
-// GELU, the residual (layers 2..5), zero outside the rod, written in place
-// as four consecutive channels per lane.
+// The epilogue of a GELU layer for the wave's M-tiles, in two halves.
+// gelu_compute: bias, GELU and the residual (layers 2..5; it reads only the
+// wave's own rows), into registers as four bfloat16 channels per lane and
+// M-tile.  It only reads the activations, so it runs before the layer's
+// barrier, while other waves (two share a SIMD) are still at their matrix
+// work: the GELU's VALU work overlaps their MFMAs.  gelu_store, after the
+// barrier (every wave done reading the layer's input): the values in place,
+// and rows outside the rod back to zero.
 template <bool RES>
-__device__ __forceinline__ void gelu_epilogue(bf16 *act, const f32x4 (&acc)[kFMT][4],
-                                              const float *bias, int wv, int lane, int w0,
-                                              int W)
+__device__ __forceinline__ void gelu_compute(const bf16 *act, const f32x4 (&acc)[kFMT][4],
+                                             const float *bias, int wv, int lane,
+                                             bf16x4 (&out)[kFMT][4])
 {
     const int r16 = lane & 15, g4 = lane >> 4;
     float bl[4][4];
@@ -137,16 +142,11 @@ __device__ __forceinline__ void gelu_epilogue(bf16 *act, const f32x4 (&acc)[kFMT
 #pragma unroll
     for (int m = 0; m < kFMT; ++m) {
         const int q = 16 * (kFMT * wv + m) + r16;          // computed row (position)
-        const int w = w0 - kFHalo + q;
-        const bool in = w >= 0 && w < W;
-        // whether all 16 rows of the M-tile lie in the rod (wave-uniform)
-        const int wt = w0 - kFHalo + 16 * (kFMT * wv + m);
-        const bool tile_in = wt >= 0 && wt + 15 < W;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            bf16x4 *dst = reinterpret_cast<bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]);
             bf16x4 hv;
-            if (RES) hv = *dst;
+            if (RES)
+                hv = *reinterpret_cast<const bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]);
             f32x4 h;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -154,19 +154,32 @@ __device__ __forceinline__ void gelu_epilogue(bf16 *act, const f32x4 (&acc)[kFMT
                 if (RES) h[j] += bf2f(hv[j]);
             }
             // two values per conversion instruction (round to nearest even)
-            *dst = __builtin_convertvector(h, bf16x4);
-        }
-        // rows outside the rod back to zero: only in the M-tiles at a rod's
-        // ends (tile_in is wave-uniform), by the lanes that wrote them
-        if (!tile_in && !in) {
-#pragma unroll
-            for (int n = 0; n < 4; ++n)
-                *reinterpret_cast<bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]) =
-                    bf16x4{f2bf(0.f), f2bf(0.f), f2bf(0.f), f2bf(0.f)};
+            out[m][n] = __builtin_convertvector(h, bf16x4);
         }
         // one M-tile at a time: no hoisting of later tiles' reads, which
         // would crowd out the registers of the weights in flight
         __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+__device__ __forceinline__ void gelu_store(bf16 *act, const bf16x4 (&out)[kFMT][4], int wv,
+                                           int lane, int w0, int W)
+{
+    const int r16 = lane & 15, g4 = lane >> 4;
+    const bf16x4 zero{f2bf(0.f), f2bf(0.f), f2bf(0.f), f2bf(0.f)};
+#pragma unroll
+    for (int m = 0; m < kFMT; ++m) {
+        const int q = 16 * (kFMT * wv + m) + r16;
+        const int w = w0 - kFHalo + q;
+        // rows outside the rod are zero (the layer-by-layer path's padding);
+        // tile_in is wave-uniform, so only the M-tiles at a rod's ends test
+        const int wt = w0 - kFHalo + 16 * (kFMT * wv + m);
+        const bool tile_in = wt >= 0 && wt + 15 < W;
+        const bool in = tile_in || (w >= 0 && w < W);
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+            *reinterpret_cast<bf16x4 *>(&act[(q + kFPad) * kFXS + 16 * n + 4 * g4]) =
+                in ? out[m][n] : zero;
     }
 }
 
@@ -216,18 +229,21 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
     }
     __syncthreads();
 
-    // layers 1..5 (GELU; residual from layer 2 on).  The next layer's
-    // weights are fetched once every wave is past the matrix work (its
-    // registers are free then) and written to LDS after the epilogue, so the
-    // loads overlap the epilogue.
+    // layers 1..5 (GELU; residual from layer 2 on).  After its matrix work a
+    // wave fetches the next layer's weights into registers and computes its
+    // epilogue values, both before the barrier, so they overlap the other
+    // waves' matrix work; after the barrier it writes the values and the
+    // weights to LDS.
     {
         f32x4 acc[kFMT][4];
+        bf16x4 outv[kFMT][4];
         {
             layer_mfma<32, 64>(act, ws, wv, lane, a.dil[0], acc);
-            __syncthreads();   // every wave has finished reading act and ws
             WeightStage<64, 64> nx;
             nx.fetch(static_cast<const bf16 *>(a.w[1]), tid);
-            gelu_epilogue<false>(act, acc, bias[0], wv, lane, w0, W);
+            gelu_compute<false>(act, acc, bias[0], wv, lane, outv);
+            __syncthreads();   // every wave has finished reading act and ws
+            gelu_store(act, outv, wv, lane, w0, W);
             nx.store(ws, tid);
             __syncthreads();
         }
@@ -235,16 +251,18 @@ __global__ __launch_bounds__(kFThreads) void jump_fused_kernel(FusedArgs a)
         for (int l = 1; l < 5; ++l) {
             layer_mfma<64, 64>(act, ws, wv, lane, a.dil[l], acc);
             if (l < 4) {
-                __syncthreads();
                 WeightStage<64, 64> nx;
                 nx.fetch(static_cast<const bf16 *>(a.w[l + 1]), tid);
-                gelu_epilogue<true>(act, acc, bias[l], wv, lane, w0, W);
+                gelu_compute<true>(act, acc, bias[l], wv, lane, outv);
+                __syncthreads();
+                gelu_store(act, outv, wv, lane, w0, W);
                 nx.store(ws, tid);
             } else {
-                __syncthreads();
                 WeightStage<64, 16> nx;
                 nx.fetch(static_cast<const bf16 *>(a.w[5]), tid);
-                gelu_epilogue<true>(act, acc, bias[l], wv, lane, w0, W);
+                gelu_compute<true>(act, acc, bias[l], wv, lane, outv);
+                __syncthreads();
+                gelu_store(act, outv, wv, lane, w0, W);
                 nx.store(ws, tid);
             }
             __syncthreads();   // activations and weights are in place

@@ -428,7 +428,8 @@ def roofline_of(prec, cfg, n, levels, steps, gpu_s, src, traffic=None):
         "kernel": kernel_name(prec, cfg, src), "depth": cfg["depth"], "launches": nl,
         "avg_launch_us": round(kernel_s * 1e6, 2),
         "avg_launch_basis": "per block of levels: the interior-tile kernel, the wall-tile "
-                            "kernel before it and the gaps (HIP events)",
+                            "kernel (beside it on a second stream for rods of many tiles, "
+                            "else before it) and the gaps (HIP events)",
         "flops_per_update": fpu,
         "algorithmic_flops_per_launch": flops,
         "issue_floor": {"peak": round(floor, 2), "frac": round(ach / floor, 4),

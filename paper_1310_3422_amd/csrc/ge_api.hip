@@ -126,10 +126,12 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // rows, few halo points and no workgroup barrier.  With a source the
 // interior tiles hold two per-parity weight arrays besides the state, so
 // the persistent schedule's prefetch registers cost more occupancy than the
-// prefetch gains, and those rods stay on one workgroup per tile: FP64 at 16
-// points per lane (142 registers, three waves per SIMD; 32 points need
-// more than the register file), FP32 at 32 (64 levels: 7.7e12 updates/s
-// against 7.4e12 at 16).
+// prefetch gains, and those rods stay on one workgroup per tile: FP64 at 28
+// points per lane and 96 levels (238 registers, two waves per SIMD; 5.9e12
+// updates/s against 5.5e12 at 16 points and three waves, the halo's share
+// of the window falling from 13% to 7%; 32 points need more than the
+// register file), FP32 at 32 (64 levels: 7.7e12 updates/s against 7.4e12
+// at 16).
 struct Choice {
     int tile, waves, depth;
 };
@@ -142,11 +144,11 @@ Choice default_choice(int prec, int depth, bool src)
         return {depth <= 64 ? 8 : 16, 4, depth};
     }
     const bool f64 = prec == ge::kFP64;
-    if (depth == 0) return src ? Choice{f64 ? 16 : 32, 1, 64} : Choice{32, 1, 96};
+    if (depth == 0) return src ? (f64 ? Choice{28, 1, 96} : Choice{32, 1, 64}) : Choice{32, 1, 96};
     if (depth <= 4) return {f64 ? 2 : 4, 1, depth};
     if (depth <= 8) return {(f64 || !src) ? (f64 ? 4 : 8) : 4, 1, depth};
     if (depth <= 16) return {f64 ? (src ? 4 : 8) : 16, 1, depth};
-    if (src) return {f64 ? 16 : 32, 1, depth};
+    if (src) return {f64 ? (depth <= 32 ? 16 : 28) : 32, 1, depth};
     if (depth <= 32) return {16, 1, depth};
     return {32, 1, depth};
 }
@@ -180,6 +182,8 @@ struct ge_plan_s {
     double c1, c2, cs, e1, e2, es, tau, h;
     ge::StatusWords status;   // word 0: a launch stored a NaN or infinite value
     bool launched;            // a kernel may hold the status pointer
+    ge::SideStream side;      // wall kernel of split launches (created on first use)
+    int side_state;           // 0 not tried, 1 created, -1 creation failed
 };
 
 namespace {
@@ -190,6 +194,10 @@ namespace {
 // widening halo (11 couples a side at k = 16 and 20 levels) catches up with
 // the saved HBM traffic.
 constexpr int kSdcDepth = 20;
+
+// Fewest tiles at which a plan keeps a second stream for split launches
+// (the split itself starts at 128 interior tiles per compute unit).
+constexpr int64_t kSideStreamTiles = 128 * 64;
 
 // The persistent form pays where one couple fills 32 FP64 registers per
 // node pair (k = 16): two waves per SIMD, so the per-tile form leaves its
@@ -410,6 +418,12 @@ void ge_destroy(ge_plan_t plan)
     if (!plan) return;
     if (plan->launched) ge::status_free(plan->status);
     else if (plan->status.host) (void)hipHostFree(plan->status.host);
+    if (plan->side_state == 1) {
+        (void)hipStreamSynchronize(plan->side.stream);
+        (void)hipEventDestroy(plan->side.fork);
+        (void)hipEventDestroy(plan->side.join);
+        (void)hipStreamDestroy(plan->side.stream);
+    }
     delete plan;
 }
 
@@ -498,6 +512,27 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
         a.nsdc = (plan->n + 1) / plan->tile;
         a.ca = plan->e1;
     }
+    // per-tile launches over many tiles may split off their wall tiles: give
+    // them a second stream (default priority) so that the wall kernel runs
+    // beside the interior one; without it they run one after the other
+    const ge::SideStream *side = nullptr;
+    if (!plan->sdc && !plan->persistent && !plan->single && plan->ntiles >= kSideStreamTiles) {
+        if (plan->side_state == 0) {
+            ge::SideStream &ss = plan->side;
+            plan->side_state = -1;
+            if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) == hipSuccess) {
+                if (hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess) {
+                    if (hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) == hipSuccess)
+                        plan->side_state = 1;
+                    else
+                        (void)hipEventDestroy(ss.fork);
+                }
+                if (plan->side_state != 1) (void)hipStreamDestroy(ss.stream);
+            }
+            (void)hipGetLastError();
+        }
+        if (plan->side_state == 1) side = &plan->side;
+    }
     // one launch of whichever kernel the plan runs
     auto launch = [&](const ge::TileArgs &la) {
         if (plan->sdc)
@@ -505,7 +540,7 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
                                     : ge::launch_sdc(plan->prec, plan->sdc, la, st);
         if (plan->persistent && !plan->single)
             return ge::launch_tiles_persistent(plan->prec, plan->tile, src, la, st);
-        return ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, la, st);
+        return ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, la, st, side);
     };
 
     if (plan->single) {

@@ -48,9 +48,18 @@ struct TileArgs {
 // Supported (precision, points per lane, waves per workgroup) choices.
 bool tile_config_supported(int prec, int k, int nw);
 
-// Enqueue one launch.  Returns hipSuccess or the launch error.
+// A second stream and two events on which a launch that splits its wall
+// tiles from its interior tiles runs the wall kernel beside the interior
+// one (forked from and joined back into the launch stream).
+struct SideStream {
+    hipStream_t stream;
+    hipEvent_t fork, join;
+};
+
+// Enqueue one launch.  Returns hipSuccess or the launch error.  side: null,
+// or a SideStream for the wall kernel of a split launch.
 hipError_t launch_tiles(int prec, int k, int nw, bool src, const TileArgs &a,
-                        hipStream_t stream);
+                        hipStream_t stream, const SideStream *side = nullptr);
 
 // Persistent single-wave form (tile_persistent_kernel): interior tiles
 // round-robin with the next tile's load overlapping the current sweep.

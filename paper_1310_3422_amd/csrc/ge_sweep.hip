@@ -146,7 +146,7 @@ hipError_t launch_persistent(const TileArgs &a, hipStream_t stream)
 }
 
 template <typename T, int K, int NW, bool COMP, bool SRC>
-hipError_t launch_one(const TileArgs &a, hipStream_t stream)
+hipError_t launch_one(const TileArgs &a, hipStream_t stream, const SideStream *side)
 {
     constexpr int64_t W = NW * kWave * K;
     // compute units (split launches only where a CU sweeps 128 tiles or more)
@@ -166,31 +166,45 @@ hipError_t launch_one(const TileArgs &a, hipStream_t stream)
                            dim3(NW * kWave), 0, stream, a);
         return hipGetLastError();
     }
+    // the wall kernel (a few workgroups, each about one tile's time) beside
+    // the interior one when a side stream is given, else before it
     const int64_t walls = 1 + (a.ntiles - tw);
+    hipError_t e = hipSuccess;
+    hipStream_t ws = stream;
+    if (side) {
+        if ((e = hipEventRecord(side->fork, stream)) != hipSuccess ||
+            (e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess)
+            return e;
+        ws = side->stream;
+    }
     hipLaunchKernelGGL((tile_kernel<T, K, NW, COMP, SRC, 2>), dim3((unsigned)walls),
-                       dim3(NW * kWave), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
+                       dim3(NW * kWave), 0, ws, a);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    if (side && (e = hipEventRecord(side->join, side->stream)) != hipSuccess)
         return e;
     const int64_t grid = (tw - 1 + 7) / 8 * 8;
     hipLaunchKernelGGL((tile_kernel<T, K, NW, COMP, SRC, 1>), dim3((unsigned)grid),
                        dim3(NW * kWave), 0, stream, a);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    return side ? hipStreamWaitEvent(stream, side->join, 0) : hipSuccess;
 }
 
 template <typename T, int K, int NW, bool COMP>
-hipError_t launch_src(bool src, const TileArgs &a, hipStream_t stream)
+hipError_t launch_src(bool src, const TileArgs &a, hipStream_t stream, const SideStream *side)
 {
-    return src ? launch_one<T, K, NW, COMP, true>(a, stream)
-               : launch_one<T, K, NW, COMP, false>(a, stream);
+    return src ? launch_one<T, K, NW, COMP, true>(a, stream, side)
+               : launch_one<T, K, NW, COMP, false>(a, stream, side);
 }
 
 template <typename T, int K, bool COMP>
-hipError_t launch_nw(int nw, bool src, const TileArgs &a, hipStream_t stream)
+hipError_t launch_nw(int nw, bool src, const TileArgs &a, hipStream_t stream,
+                     const SideStream *side)
 {
     switch (nw) {
-    case 1: return launch_src<T, K, 1, COMP>(src, a, stream);
-    case 4: return launch_src<T, K, 4, COMP>(src, a, stream);
+    case 1: return launch_src<T, K, 1, COMP>(src, a, stream, side);
+    case 4: return launch_src<T, K, 4, COMP>(src, a, stream, side);
     default: return hipErrorInvalidValue;
     }
 }
@@ -253,7 +267,9 @@ bool tile_config_supported(int prec, int k, int nw)
     if (nw != 1 && nw != 4)
         return false;
     switch (prec) {
-    case kFP64: return k == 2 || k == 4 || k == 8 || k == 16 || k == 32 || k == 64;
+    case kFP64:
+        return k == 2 || k == 4 || k == 8 || k == 16 || k == 20 || k == 24 || k == 28 || k == 32 ||
+               k == 64;
     case kFP32: return k == 4 || k == 8 || k == 16 || k == 32;
     case kFP32C: return k == 4 || k == 8 || k == 16;
     default: return false;
@@ -261,27 +277,30 @@ bool tile_config_supported(int prec, int k, int nw)
 }
 
 hipError_t launch_tiles(int prec, int k, int nw, bool src, const TileArgs &a,
-                        hipStream_t stream)
+                        hipStream_t stream, const SideStream *side)
 {
     switch (prec) {
     case kFP64:
-        if (k == 2) return launch_nw<double, 2, false>(nw, src, a, stream);
-        if (k == 4) return launch_nw<double, 4, false>(nw, src, a, stream);
-        if (k == 8) return launch_nw<double, 8, false>(nw, src, a, stream);
-        if (k == 16) return launch_nw<double, 16, false>(nw, src, a, stream);
-        if (k == 32) return launch_nw<double, 32, false>(nw, src, a, stream);
-        if (k == 64) return launch_nw<double, 64, false>(nw, src, a, stream);
+        if (k == 2) return launch_nw<double, 2, false>(nw, src, a, stream, side);
+        if (k == 4) return launch_nw<double, 4, false>(nw, src, a, stream, side);
+        if (k == 8) return launch_nw<double, 8, false>(nw, src, a, stream, side);
+        if (k == 16) return launch_nw<double, 16, false>(nw, src, a, stream, side);
+        if (k == 20) return launch_nw<double, 20, false>(nw, src, a, stream, side);
+        if (k == 24) return launch_nw<double, 24, false>(nw, src, a, stream, side);
+        if (k == 28) return launch_nw<double, 28, false>(nw, src, a, stream, side);
+        if (k == 32) return launch_nw<double, 32, false>(nw, src, a, stream, side);
+        if (k == 64) return launch_nw<double, 64, false>(nw, src, a, stream, side);
         break;
     case kFP32:
-        if (k == 4) return launch_nw<float, 4, false>(nw, src, a, stream);
-        if (k == 8) return launch_nw<float, 8, false>(nw, src, a, stream);
-        if (k == 16) return launch_nw<float, 16, false>(nw, src, a, stream);
-        if (k == 32) return launch_nw<float, 32, false>(nw, src, a, stream);
+        if (k == 4) return launch_nw<float, 4, false>(nw, src, a, stream, side);
+        if (k == 8) return launch_nw<float, 8, false>(nw, src, a, stream, side);
+        if (k == 16) return launch_nw<float, 16, false>(nw, src, a, stream, side);
+        if (k == 32) return launch_nw<float, 32, false>(nw, src, a, stream, side);
         break;
     case kFP32C:
-        if (k == 4) return launch_nw<float, 4, true>(nw, src, a, stream);
-        if (k == 8) return launch_nw<float, 8, true>(nw, src, a, stream);
-        if (k == 16) return launch_nw<float, 16, true>(nw, src, a, stream);
+        if (k == 4) return launch_nw<float, 4, true>(nw, src, a, stream, side);
+        if (k == 8) return launch_nw<float, 8, true>(nw, src, a, stream, side);
+        if (k == 16) return launch_nw<float, 16, true>(nw, src, a, stream, side);
         break;
     }
     return hipErrorInvalidValue;

@@ -261,9 +261,9 @@ def test_plan_schedule_validation():
 
 
 @pytest.mark.parametrize("prec,depth,src,want", [
-    (0, 0, False, (32, 1, 96, 2)), (0, 0, True, (16, 1, 64, 1)),
+    (0, 0, False, (32, 1, 96, 2)), (0, 0, True, (28, 1, 96, 1)),
     (0, 1, False, (2, 1, 1, 1)), (0, 8, True, (4, 1, 8, 1)), (0, 16, False, (8, 1, 16, 1)),
-    (0, 32, True, (16, 1, 32, 1)), (0, 64, False, (32, 1, 64, 2)), (0, 64, True, (16, 1, 64, 1)),
+    (0, 32, True, (16, 1, 32, 1)), (0, 64, False, (32, 1, 64, 2)), (0, 64, True, (28, 1, 64, 1)),
     (1, 0, False, (32, 1, 96, 2)), (1, 4, False, (4, 1, 4, 1)), (1, 8, False, (8, 1, 8, 1)),
     (1, 8, True, (4, 1, 8, 1)), (1, 16, True, (16, 1, 16, 1)), (1, 64, True, (32, 1, 64, 1)),
     (1, 0, True, (32, 1, 64, 1)), (1, 32, True, (32, 1, 32, 1)),

@@ -130,7 +130,7 @@ def test_bitwise_invariance_across_tiling_depth_and_calls(precision):
     n, s = 30011, 40
     rng = np.random.default_rng(17)
     u0 = inputs.sine_rod(n, 17) + 0.05 * rng.standard_normal(n)
-    tiles = {"fp64": (2, 4, 8, 16, 32, 64), "fp32": (4, 8, 16, 32), "fp32c": (4, 8, 16)}[precision]
+    tiles = {"fp64": (2, 4, 8, 16, 20, 24, 28, 32, 64), "fp32": (4, 8, 16, 32), "fp32c": (4, 8, 16)}[precision]
     results = []
     for tile in tiles:
         for waves in (1, 4):
@@ -324,3 +324,19 @@ def test_split_wall_launch_is_bitwise_the_single_launch(precision):
                             src_a=w.src_a, flux=True, **cfg))
     np.testing.assert_array_equal(runs[0][0], runs[1][0])
     np.testing.assert_array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("tile,waves,depth", [(20, 1, 64), (20, 4, 23), (16, 1, 64), (24, 1, 64),
+                                              (28, 1, 80), (28, 4, 31)])
+def test_source_tiles_bitwise(tile, waves, depth):
+    """FP64 with moving walls and a source: every tile, wave count and depth
+    gives the bits of a reference plan (8 points per lane, 9 levels)."""
+    n, s = 300007, 130
+    w = inputs.moving_wall_rod(n, r=4.0, nsteps=s, step0=2)
+    u0 = inputs.sine_rod(n, 3) + 0.05 * np.random.default_rng(3).standard_normal(n)
+    ref, fref = run_gpu(u0, 4.0, s, "fp64", step0=2, gl=w.g_left, gr=-0.3, src_b=w.src_b,
+                        src_a=w.src_a, flux=True, tile=8, waves=1, depth=9)
+    got, fgot = run_gpu(u0, 4.0, s, "fp64", step0=2, gl=w.g_left, gr=-0.3, src_b=w.src_b,
+                        src_a=w.src_a, flux=True, tile=tile, waves=waves, depth=depth)
+    np.testing.assert_array_equal(got, ref)
+    np.testing.assert_array_equal(fgot, fref)

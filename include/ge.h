@@ -97,7 +97,8 @@ typedef struct {
     int32_t precision;  /* ge_precision                                       */
     int32_t tile;       /* points per lane (even; 0 = the library's choice)   */
     int32_t depth;      /* levels fused per launch (>= 1; 0 = library choice) */
-    int32_t waves;      /* waves per workgroup (1 or 4; 0 = library choice)   */
+    int32_t waves;      /* waves per workgroup (1 or 4, with k >= 2 also 2    */
+                        /* and 8; 0 = library choice)                         */
     double g_left;      /* wall value g_L, used when a call gives no array    */
     double g_right;     /* wall value g_R, likewise                           */
     const void *src_b;  /* device, n values of the state's element type       */
@@ -106,7 +107,8 @@ typedef struct {
     int32_t schedule;   /* 0 = library choice; 1 = one workgroup per tile per */
                         /* launch; 2 = persistent single-wave workgroups that */
                         /* sweep several tiles each, loading the next tile    */
-                        /* during the current one (waves must be 1)           */
+                        /* during the current one (waves must be 1, except    */
+                        /* for the sub-domain scheme: see k)                  */
     int32_t k;          /* sub-domain width (Section 2): 0 or 1 = two-point   */
                         /* groups, the sweep described above; 2, 4, 8 or 16 = */
                         /* odd and even sub-domains of k nodes, Eq. (3)/(4)   */
@@ -116,10 +118,14 @@ typedef struct {
                         /* no flux; levels of even index take the pairs where */
                         /* sub-domain couples meet, odd ones the pairs at     */
                         /* their centres.  One couple (2k nodes) per lane,    */
-                        /* 64 per window; tile must be 0 or 2k, waves 0 or 1. */
-                        /* Schedule 2 here: resident single-wave workgroups   */
-                        /* that copy the next window from HBM into LDS while  */
-                        /* the current one advances (used from 3 windows on); */
+                        /* 64 per wave, windows of 1, 2, 4 or 8 waves (waves  */
+                        /* 0, 1, 2, 4 or 8; the waves of a window exchange    */
+                        /* their edge values through LDS once per level);     */
+                        /* tile must be 0 or 2k.  Schedule 2 here: resident   */
+                        /* workgroups of `waves` waves that copy the          */
+                        /* next window from HBM into LDS while the current    */
+                        /* one advances (used from 3 windows on; at most 64   */
+                        /* levels per launch, else GE_ERR_INVALID);           */
                         /* the library's choice takes it for GE_FP64 with     */
                         /* k = 16 from 64 windows on, at 24 levels per launch */
                         /* (20 otherwise).                                    */

@@ -188,12 +188,6 @@ struct ge_plan_s {
 
 namespace {
 
-// Levels per launch of the sub-domain scheme when the caller leaves it to
-// the library: measured on MI355X (2^24 points, k = 8 and 16, FP64 and
-// FP32), updates/s rise with the depth up to 16-24 levels, where the
-// widening halo (11 couples a side at k = 16 and 20 levels) catches up with
-// the saved HBM traffic.
-constexpr int kSdcDepth = 20;
 
 // Fewest tiles at which a plan keeps a second stream for split launches
 // (the split itself starts at 128 interior tiles per compute unit).
@@ -201,17 +195,50 @@ constexpr int64_t kSideStreamTiles = 128 * 64;
 
 // The persistent form pays where one couple fills 32 FP64 registers per
 // node pair (k = 16): two waves per SIMD, so the per-tile form leaves its
-// loads exposed.  Measured there 5-9% faster at 16-24 levels; at k <= 8, or
-// in FP32 (four waves per SIMD), the per-tile form is as fast or faster.
-// The persistent grid takes whole rounds of tiles, so the depth is the one
-// whose tile count left the last round nearly full at 2^24 points (24).
+// loads exposed.  Measured there 2-9% faster; at k <= 8, or in FP32, the
+// per-tile form is as fast or faster.
 bool sdc_persistent_pays(int prec, int k) { return prec == ge::kFP64 && k == 16; }
-constexpr int kSdcPersistentDepth = 24;
 constexpr int64_t kSdcPersistentMinTiles = 64;
 
 // Halo, in sub-domain couples, for D levels: a wrong value at an open window
 // edge moves at most k + 1 nodes per level, two more for the pair stencil.
 int sdc_halo(int depth, int k) { return (depth * (k + 1) + 2 + 2 * k - 1) / (2 * k); }
+
+// Levels per launch of the sub-domain scheme for a window of `waves` waves
+// when the caller leaves the depth to the library.  The halo per side
+// (about D/2 couples) does not depend on the window, so wider windows pay
+// for deeper launches.  Measured on MI355X on rods of 2^24 - 1 points (960
+// levels, k = 2..16, FP64 and FP32): single-wave windows peak at 20 levels
+// (24 persistent), two waves at 24, four at 40, eight at 48 (64 for FP64
+// with k = 16).
+int sdc_default_depth(int prec, int k, int waves)
+{
+    const bool wide64 = prec == ge::kFP64 && k == 16;
+    switch (waves) {
+    case 1: return wide64 ? 24 : 20;
+    case 2: return 24;
+    case 4: return 40;
+    default: return wide64 ? 64 : 48;
+    }
+}
+
+// Waves per window when the caller leaves them to the library: the widest
+// window measured fastest on 2^24 - 1 points (FP64 with k = 16: four waves
+// at 40 levels, persistent, 4.7e12 updates/s against 3.7e12 single-wave;
+// otherwise eight at 48 levels, per tile: FP64 k = 8 5.2e12 against 3.7e12,
+// FP32 k = 16 9.1e12 against 6.0e12), as long as the rod gives that launch
+// at least 8192 waves (4 per SIMD at two resident); shorter rods keep
+// single-wave windows, whose many small tiles spread over the chip.
+int sdc_default_waves(int prec, int k, int64_t nsdc, int depth_given)
+{
+    const int wide = (prec == ge::kFP64 && k == 16) ? 4 : 8;
+    const int depth = depth_given ? depth_given : sdc_default_depth(prec, k, wide);
+    const int64_t core = 64 * wide - 2 * (int64_t)sdc_halo(depth, k);
+    if (core < 16)
+        return 1;
+    const int64_t tiles = (nsdc + core - 1) / core;
+    return tiles * wide >= 8192 ? wide : 1;
+}
 
 ge_status plan_sdc(ge_plan_t *out, const ge_desc *d)
 {
@@ -229,21 +256,32 @@ ge_status plan_sdc(ge_plan_t *out, const ge_desc *d)
     if (d->tile != 0 && d->tile != 2 * k)
         return fail(GE_ERR_INVALID, "ge_plan: the sub-domain scheme holds 2k = %d points per lane",
                     2 * k);
-    if (d->waves != 0 && d->waves != 1)
-        return fail(GE_ERR_INVALID, "ge_plan: the sub-domain scheme runs single-wave windows");
+    if (d->waves != 0 && !ge::sdc_waves_supported(d->waves))
+        return fail(GE_ERR_INVALID, "ge_plan: the sub-domain scheme runs windows of 1, 2, 4 or 8 waves");
     if (d->schedule < 0 || d->schedule > 2)
         return fail(GE_ERR_INVALID, "ge_plan: schedule = %d, need 0, 1 or 2", d->schedule);
+    if (d->depth < 0)
+        return fail(GE_ERR_INVALID, "ge_plan: depth = %d, need depth >= 1", d->depth);
     const bool auto_persistent = d->schedule == 0 && sdc_persistent_pays(prec, k);
-    const int depth = d->depth != 0 ? d->depth : auto_persistent ? kSdcPersistentDepth : kSdcDepth;
-    if (depth < 1)
-        return fail(GE_ERR_INVALID, "ge_plan: depth = %d, need depth >= 1", depth);
     const int64_t nsdc = (d->n + 1) / (2 * k);
-    const int halo = sdc_halo(depth, k);
-    const bool single = nsdc <= 64;
-    if (!single && 64 - 2 * halo < 16)
+    const int waves = d->waves != 0 ? d->waves : sdc_default_waves(prec, k, nsdc, d->depth);
+    int depth = d->depth;
+    if (depth == 0) {
+        depth = sdc_default_depth(prec, k, waves);
+        // single-wave per-tile launches keep 20 levels (24 is the persistent one's)
+        if (waves == 1 && !auto_persistent && d->schedule != 2) depth = 20;
+    }
+    if (d->schedule == 2 && depth > ge::kSdcMaxLevels)
         return fail(GE_ERR_INVALID,
-                    "ge_plan: depth %d needs a halo of %d couples, too wide for 64-couple windows",
-                    depth, halo);
+                    "ge_plan: the persistent sub-domain form takes at most %d levels per launch",
+                    ge::kSdcMaxLevels);
+    const int halo = sdc_halo(depth, k);
+    const int wsdc = 64 * waves;            // couples per window
+    const bool single = nsdc <= wsdc;
+    if (!single && wsdc - 2 * halo < 16)
+        return fail(GE_ERR_INVALID,
+                    "ge_plan: depth %d needs a halo of %d couples, too wide for %d-couple windows",
+                    depth, halo, wsdc);
     ge_plan_s *p = new (std::nothrow) ge_plan_s();
     if (!p)
         return fail(GE_ERR_NOMEM, "ge_plan: out of host memory");
@@ -252,15 +290,15 @@ ge_status plan_sdc(ge_plan_t *out, const ge_desc *d)
     p->prec = prec;
     p->sdc = k;
     p->tile = 2 * k;
-    p->waves = 1;
+    p->waves = waves;
     p->depth = depth;
-    p->window = 64 * 2 * (int64_t)k;
+    p->window = (int64_t)wsdc * 2 * k;
     p->g_left = d->g_left;
     p->g_right = d->g_right;
     p->src_b = nullptr;
     p->single = single;
     p->halo = single ? 0 : halo;          // in couples
-    p->core = single ? nsdc : 64 - 2 * halo;
+    p->core = single ? nsdc : wsdc - 2 * halo;
     p->ntiles = (nsdc + p->core - 1) / p->core;
     p->persistent = !single && p->ntiles >= 3 &&
                     (d->schedule == 2 || (auto_persistent && p->ntiles >= kSdcPersistentMinTiles));
@@ -536,8 +574,9 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
     // one launch of whichever kernel the plan runs
     auto launch = [&](const ge::TileArgs &la) {
         if (plan->sdc)
-            return plan->persistent ? ge::launch_sdc_persistent(plan->prec, plan->sdc, la, st)
-                                    : ge::launch_sdc(plan->prec, plan->sdc, la, st);
+            return plan->persistent
+                       ? ge::launch_sdc_persistent(plan->prec, plan->sdc, plan->waves, la, st)
+                       : ge::launch_sdc(plan->prec, plan->sdc, plan->waves, la, st);
         if (plan->persistent && !plan->single)
             return ge::launch_tiles_persistent(plan->prec, plan->tile, src, la, st);
         return ge::launch_tiles(plan->prec, plan->tile, plan->waves, src, la, st, side);

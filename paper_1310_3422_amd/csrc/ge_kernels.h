@@ -68,12 +68,16 @@ hipError_t launch_tiles_persistent(int prec, int k, bool src, const TileArgs &a,
                                    hipStream_t stream);
 
 // Sub-domain scheme with sub-domains of k = K/2 nodes, one sub-domain couple
-// (K nodes) per lane, single-wave windows of 64 couples (ge_sdc.hip).
+// (K nodes) per lane, windows of nw x 64 couples, nw waves per workgroup
+// exchanging edge values through LDS (ge_sdc.hip).
 bool sdc_supported(int prec, int k);
-hipError_t launch_sdc(int prec, int k, const TileArgs &a, hipStream_t stream);
-// Persistent form of the same (needs ntiles >= 3 and out != in): resident
-// single-wave workgroups, the next window copied into LDS during the levels.
-hipError_t launch_sdc_persistent(int prec, int k, const TileArgs &a, hipStream_t stream);
+bool sdc_waves_supported(int nw);
+hipError_t launch_sdc(int prec, int k, int nw, const TileArgs &a, hipStream_t stream);
+// Persistent form of the same (needs ntiles >= 3, out != in and at most
+// kSdcMaxLevels levels): resident workgroups, the next window copied into
+// LDS during the levels.
+constexpr int kSdcMaxLevels = 64;
+hipError_t launch_sdc_persistent(int prec, int k, int nw, const TileArgs &a, hipStream_t stream);
 
 // Elementwise conversions for the compensated pair.
 hipError_t launch_comp_to_fp64(const float *pair, double *x, int64_t n, hipStream_t s);

@@ -23,12 +23,14 @@
 // form; a sweep step is fma(c, v_prev, fma(ca, w, c w_other)), c = r/(1+r),
 // ca = (1-r)/(1+r), taken two nodes at a time (see sweep_run).
 //
-// Temporal blocking: a launch advances `nlev` levels of a window of 64 SDCs
-// and writes back its core; the window moves through LDS on the way in and
-// out, so that HBM sees consecutive 16-byte chunks across the lanes.  A wrong value at an open window edge spreads at
-// most k + 1 nodes per level (through a sweep), so the halo is
+// Temporal blocking: a launch advances `nlev` levels of a window of NW x 64
+// SDCs (NW waves of one workgroup) and writes back its core; the window
+// moves through LDS on the way in and out, so that HBM sees consecutive
+// 16-byte chunks across the lanes.  A wrong value at an open window edge
+// spreads at most k + 1 nodes per level (through a sweep), so the halo is
 // ceil((D (k+1) + 2) / K) whole SDCs on each side (measured tight to within
-// one SDC on the CPU against the oracle).
+// one SDC on the CPU against the oracle), whatever the window's width: wider
+// windows recompute a smaller share of halo.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -106,19 +108,76 @@ __device__ __forceinline__ T sweep_run(T (&s)[K], T v, const SdcCoef<T> &k, Othe
     return v;
 }
 
+// Values that cross a wave's edges.  A level needs, besides its own lanes,
+// one value from each side: at even levels the right neighbour's element 0
+// before the level and the left neighbour's new element K-1 (its pair's
+// right value) half-way through; at odd levels the left neighbour's element
+// K-1 before the level and the right neighbour's new element 0 at its end.
+// Each of the two mid-level values is also the other side's start value of
+// the next level, so a window of NW waves exchanges its waves' edge lanes
+// through LDS once per level (one barrier), plus once when a window is
+// loaded.  Lanes 0 and 63 of the window's outer waves take zeros, which
+// reach only the halo; a single-wave window (NW = 1) exchanges nothing.
+template <typename T, int NW>
+struct SdcEdge {
+    T (*slot)[NW][2];    // [3][NW][2] in LDS: per level parity, and at load
+    int w;               // this wave in the workgroup
+    T xr0 = T(0);        // right wave's element 0 of lane 0, current level
+    T xl63 = T(0);       // left wave's element K-1 of lane 63, current level
+
+    // a window's registers are loaded: both start values
+    template <int K>
+    __device__ __forceinline__ void start(int lane, const T (&s)[K])
+    {
+        if constexpr (NW > 1) {
+            if (lane == 0) slot[2][w][0] = s[0];
+            if (lane == kWave - 1) slot[2][w][1] = s[K - 1];
+            __syncthreads();
+            xr0 = w < NW - 1 ? slot[2][w + 1][0] : T(0);
+            xl63 = w > 0 ? slot[2][w - 1][1] : T(0);
+        }
+    }
+    // even level, mid-way: lane 63's new pair value to the right wave
+    __device__ __forceinline__ T mid_left(int lane, int buf, T pb)
+    {
+        if constexpr (NW > 1) {
+            if (lane == kWave - 1) slot[buf][w][1] = pb;
+            __syncthreads();
+            xl63 = w > 0 ? slot[buf][w - 1][1] : T(0);
+            return xl63;
+        } else {
+            return T(0);
+        }
+    }
+    // odd level, at its end: lane 0's new element 0 to the left wave
+    __device__ __forceinline__ T end_right(int lane, int buf, T s0)
+    {
+        if constexpr (NW > 1) {
+            if (lane == 0) slot[buf][w][0] = s0;
+            __syncthreads();
+            xr0 = w < NW - 1 ? slot[buf][w + 1][0] : T(0);
+            return xr0;
+        } else {
+            return T(0);
+        }
+    }
+};
+
 // One level of the lane's SDC.  first / last: the lane holds the rod's first
 // / last SDC (walls); gl_old, gl_new: left wall at this and the next level;
-// gr_new: right wall at the next level.  Values entering from lanes outside
-// the window are zero: they only reach the halo.
-template <typename T, int K, int KIND>
+// gr_new: right wall at the next level.  Values entering the wave from
+// outside come from `edge` (zeros at the window's open edges: they only
+// reach the halo); buf: the level's exchange slot (its parity in the launch).
+template <typename T, int K, int KIND, int NW>
 __device__ __forceinline__ void sdc_level(T (&s)[K], const SdcCoef<T> &cf, bool first, bool last,
-                                          T gl_old, T gl_new, T gr_new)
+                                          T gl_old, T gl_new, T gr_new, SdcEdge<T, NW> &edge,
+                                          int lane, int buf)
 {
     constexpr int k = K / 2;
     static_assert(k >= 2, "sub-domains of two or more nodes");
     if constexpr (KIND == 1) {
         // pair at the boundary with the next SDC: elements K-2, K-1
-        const T oR = from_right(T(0), s[0]);
+        const T oR = from_right(edge.xr0, s[0]);
         T pA, pB;
         sdc_pair(s[K - 3], s[K - 2], s[K - 1], oR, cf, pA, pB);
         if (last) {
@@ -128,7 +187,7 @@ __device__ __forceinline__ void sdc_level(T (&s)[K], const SdcCoef<T> &cf, bool 
         }
         // scheme A through the odd sub-domain, from its first node (the
         // left lane's pair value, or the left wall)
-        T v = from_left(T(0), pB);
+        T v = from_left(edge.mid_left(lane, buf, pB), pB);
         if (first) v = gl_new;
         const T o_odd_last = s[k - 2];
         sweep_run<T, K, 0, k - 2>(s, v, cf, [&](int e) { return s[e + 1]; });
@@ -139,7 +198,7 @@ __device__ __forceinline__ void sdc_level(T (&s)[K], const SdcCoef<T> &cf, bool 
         s[K - 1] = pB;
     } else {
         // node iK (this SDC's first node) lives in the left lane
-        const T fl = from_left(T(0), s[K - 1]);
+        const T fl = from_left(edge.xl63, s[K - 1]);
         const T oL = first ? gl_old : fl;
         // pair at the centre: elements k-2, k-1
         T qA, qB;
@@ -154,7 +213,7 @@ __device__ __forceinline__ void sdc_level(T (&s)[K], const SdcCoef<T> &cf, bool 
         s[k - 1] = qB;
         // element K-1 is the first node of the next SDC, the end of its
         // scheme-B sweep: it needs that lane's new element 0
-        const T r0 = from_right(T(0), s[0]);
+        const T r0 = from_right(edge.end_right(lane, buf, s[0]), s[0]);
         const T nk = sweep(r0, o_last, o_prev, cf);
         s[K - 1] = last ? gr_new : nk;
     }
@@ -180,7 +239,7 @@ __device__ __forceinline__ void stage_load(const T *__restrict__ in, int64_t bas
 {
     using S = Stage<T, K>;
     using V = typename V16<T>::type;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int j = 0; j < S::CH / kWave; ++j) {
         const int c = j * kWave + lane;               // chunk of the window
@@ -220,7 +279,7 @@ __device__ __forceinline__ void stage_store(T *__restrict__ out, int64_t base, i
 {
     using S = Stage<T, K>;
     using V = typename V16<T>::type;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
     V *row = reinterpret_cast<V *>(&lds[lane * S::P]);
 #pragma unroll
     for (int q = 0; q < K / S::E; ++q) {
@@ -259,41 +318,53 @@ __device__ __forceinline__ void stage_store(T *__restrict__ out, int64_t base, i
     }
 }
 
-template <typename T, int K>
-__global__ __launch_bounds__(kWave) void sdc_tile_kernel(TileArgs a)
+// window positions [c0, c1) of the core, as values of the part of wave w
+// (SDCs wb .. wb+63), clipped to the part
+__device__ __forceinline__ int part_pos(int64_t c, int64_t wb, int K)
+{
+    const int64_t e = (c - wb) * K;
+    return e < 0 ? 0 : e > (int64_t)kWave * K ? kWave * K : (int)e;
+}
+
+template <typename T, int K, int NW>
+__global__ __launch_bounds__(NW * kWave) void sdc_tile_kernel(TileArgs a)
 {
     // consecutive tiles on one XCD, as in the two-point sweep
     const int64_t per = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (t >= a.ntiles)
         return;
-    const int lane = threadIdx.x;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t c0 = t * a.core;                              // first core SDC
     const int64_t w0 = c0 - a.halo < 0 ? 0 : c0 - a.halo;       // first SDC of the window
-    const int64_t i = w0 + lane;                                // this lane's SDC
+    const int64_t wb = w0 + (int64_t)w * kWave;                 // first SDC of this wave
+    const int64_t i = wb + lane;                                // this lane's SDC
     const T *in = static_cast<const T *>(a.in);
     T *out = static_cast<T *>(a.out);
-    __shared__ __attribute__((aligned(16))) T lds[kWave * Stage<T, K>::P];
+    __shared__ __attribute__((aligned(16))) T lds[NW][kWave * Stage<T, K>::P];
+    __shared__ T slot[3][NW][2];
     T s[K];
-    stage_load<T, K>(in, w0 * K, a.n, lds, s);
+    stage_load<T, K>(in, wb * K, a.n, lds[w], s);
     const bool first = (i == 0), last = (i == a.nsdc - 1);
     auto gl = [&](int lev) { return a.gl_t ? a.gl_t[lev] : a.gl0; };
     auto gr = [&](int lev) { return a.gr_t ? a.gr_t[lev] : a.gr0; };
     if (last) s[K - 1] = (T)gr(0);
     const SdcCoef<T> cf = sdc_lane_coef(SdcCoef<T>{(T)a.cs, (T)a.ca, (T)a.c1, (T)a.c2});
+    SdcEdge<T, NW> edge{slot, w};
+    edge.start(lane, s);
     for_levels(a.level0, a.nlev, [&](auto par, int lev) {
         constexpr int p = decltype(par)::value;
-        sdc_level<T, K, p == 0 ? 1 : 2>(s, cf, first, last, (T)gl(lev), (T)gl(lev + 1),
-                                         (T)gr(lev + 1));
+        sdc_level<T, K, p == 0 ? 1 : 2, NW>(s, cf, first, last, (T)gl(lev), (T)gl(lev + 1),
+                                             (T)gr(lev + 1), edge, lane, lev & 1);
     });
     const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
     T fin = T(0);
-    stage_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds, s, fin);
+    stage_store<T, K>(out, wb * K, a.n, part_pos(c0, wb, K), part_pos(c1, wb, K), lds[w], s, fin);
     raise_if_nonfinite(a.status, fin);
 }
 
-// Persistent form.  Single-wave workgroups stay resident and take the tiles
-// round by round; while a tile advances through its levels, the next tile's
+// Persistent form.  Workgroups of NW waves stay resident and take the tiles
+// round by round (each wave the same 64-SDC part of every window); while a tile advances through its levels, the next tile's
 // window is copied from HBM straight into the wave's LDS buffer
 // (global_load_lds: no registers held), so the HBM traffic of a launch
 // hides behind its arithmetic instead of alternating with it.  When the
@@ -323,6 +394,14 @@ struct Swz {
 
 using lds_void = __attribute__((address_space(3))) void;
 
+// One 16-byte chunk per lane from global memory straight into LDS.  (A plain
+// function: the builtin exists only for the device, and the host pass would
+// otherwise reject every use of a template that calls it but the first.)
+__device__ __forceinline__ void copy16_to_lds(const void *src, void *dst)
+{
+    __builtin_amdgcn_global_load_lds(src, (lds_void *)dst, 16, 0, 0);
+}
+
 // Issue the copy of window values base .. base + 64K of `in` into the
 // buffer.  A chunk that reaches past the rod is replaced by chunk 0 (any
 // valid address; tail_fix overwrites those values).
@@ -331,12 +410,12 @@ __device__ __forceinline__ void dma_window(const T *__restrict__ in, int64_t bas
                                            T *lds)
 {
     using S = Swz<T, K>;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int j = 0; j < S::Q; ++j) {
         const int64_t g = base + (int64_t)S::chunk(j * kWave + lane) * S::E;
         const T *src = g + S::E <= n ? in + g : in;
-        __builtin_amdgcn_global_load_lds(src, (lds_void *)(lds + j * kWave * S::E), 16, 0, 0);
+        copy16_to_lds(src, lds + j * kWave * S::E);
     }
 }
 
@@ -370,7 +449,7 @@ __device__ __forceinline__ void rows_read(const T *lds, T (&s)[K])
 {
     using S = Swz<T, K>;
     using V = typename V16<T>::type;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int q = 0; q < S::Q; ++q)
         unpack<T, K>(*reinterpret_cast<const V *>(&lds[S::slot(lane, q) * S::E]), s, q);
@@ -382,7 +461,7 @@ __device__ __forceinline__ void rows_write(T *lds, const T (&s)[K])
 {
     using S = Swz<T, K>;
     using V = typename V16<T>::type;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int q = 0; q < S::Q; ++q)
         *reinterpret_cast<V *>(&lds[S::slot(lane, q) * S::E]) = pack<T, K>(s, q);
@@ -395,7 +474,7 @@ __device__ __forceinline__ void rows_swap(T *lds, T (&s)[K])
 {
     using S = Swz<T, K>;
     using V = typename V16<T>::type;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int q = 0; q < S::Q; ++q) {
         V *p = reinterpret_cast<V *>(&lds[S::slot(lane, q) * S::E]);
@@ -412,7 +491,7 @@ __device__ __forceinline__ void chunks_store(T *__restrict__ out, int64_t base, 
 {
     using S = Swz<T, K>;
     using V = typename V16<T>::type;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
 #pragma unroll
     for (int j = 0; j < S::Q; ++j) {
         const int sl = j * kWave + lane;
@@ -448,7 +527,7 @@ __device__ __forceinline__ void tail_fix(const T *__restrict__ in, int64_t base,
 {
     if (base + (int64_t)kWave * K <= n)
         return;
-    const int64_t b = base + (int64_t)threadIdx.x * K;
+    const int64_t b = base + (int64_t)(threadIdx.x % kWave) * K;
     T v[K];
 #pragma unroll
     for (int e = 0; e < K; ++e)
@@ -456,32 +535,33 @@ __device__ __forceinline__ void tail_fix(const T *__restrict__ in, int64_t base,
     rows_write<T, K>(lds, v);
 }
 
-// levels per launch of the persistent form (the wall values of a launch
-// sit in LDS)
-constexpr int kSdcMaxLevels = 64;
-
-template <typename T, int K>
-__global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int nwg)
+template <typename T, int K, int NW>
+__global__ __launch_bounds__(NW * kWave) void sdc_persistent_kernel(TileArgs a, int nwg)
 {
-    __shared__ __attribute__((aligned(16))) T lds[kWave * K];
+    __shared__ __attribute__((aligned(16))) T lds_all[NW][kWave * K];
     __shared__ double walls[2][kSdcMaxLevels + 1];
+    __shared__ T slot[3][NW][2];
     const int per = nwg / 8;
     int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-aware
     if (t >= a.ntiles)
         return;
-    const int lane = threadIdx.x;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    T *lds = lds_all[w];
     const T *in = static_cast<const T *>(a.in);
     T *out = static_cast<T *>(a.out);
+    // first SDC of this wave's part of tile tt's window
     auto wstart = [&](int64_t tt) {
         const int64_t c0 = tt * a.core;
-        return c0 - a.halo < 0 ? (int64_t)0 : c0 - a.halo;
+        return (c0 - a.halo < 0 ? (int64_t)0 : c0 - a.halo) + (int64_t)w * kWave;
     };
     // The wall values of the launch's levels, read once: inside the loop
     // every wait on vector memory would also wait for the pending copy.
-    for (int j = lane; j <= a.nlev; j += kWave) {
+    for (int j = threadIdx.x; j <= a.nlev; j += NW * kWave) {
         walls[0][j] = a.gl_t ? a.gl_t[j] : a.gl0;
         walls[1][j] = a.gr_t ? a.gr_t[j] : a.gr0;
     }
+    if constexpr (NW > 1)
+        __syncthreads();
     auto gl = [&](int lev) { return walls[0][lev]; };
     auto gr = [&](int lev) { return walls[1][lev]; };
     T s[K];
@@ -490,20 +570,22 @@ __global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int n
     tail_fix<T, K>(in, wstart(t) * K, a.n, lds);
     rows_read<T, K>(lds, s);
     const SdcCoef<T> cf = sdc_lane_coef(SdcCoef<T>{(T)a.cs, (T)a.ca, (T)a.c1, (T)a.c2});
+    SdcEdge<T, NW> edge{slot, w};
     for (;;) {
-        const int64_t w0 = wstart(t);
+        const int64_t wb = wstart(t);
         const int64_t tn = t + nwg;
         const bool more = tn < a.ntiles;
         wait_lds();
         if (more)
             dma_window<T, K>(in, wstart(tn) * K, a.n, lds);
-        const int64_t i = w0 + lane;
+        const int64_t i = wb + lane;
         const bool first = (i == 0), last = (i == a.nsdc - 1);
         if (last) s[K - 1] = (T)gr(0);
+        edge.start(lane, s);
         for_levels(a.level0, a.nlev, [&](auto par, int lev) {
             constexpr int p = decltype(par)::value;
-            sdc_level<T, K, p == 0 ? 1 : 2>(s, cf, first, last, (T)gl(lev), (T)gl(lev + 1),
-                                             (T)gr(lev + 1));
+            sdc_level<T, K, p == 0 ? 1 : 2, NW>(s, cf, first, last, (T)gl(lev), (T)gl(lev + 1),
+                                                 (T)gr(lev + 1), edge, lane, lev & 1);
         });
         const int64_t c0 = t * a.core;
         const int64_t c1 = c0 + a.core < a.nsdc ? c0 + a.core : a.nsdc;
@@ -515,7 +597,7 @@ __global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int n
             rows_write<T, K>(lds, s);
         }
         T fin = T(0);
-        chunks_store<T, K>(out, w0 * K, a.n, (int)((c0 - w0) * K), (int)((c1 - w0) * K), lds, fin);
+        chunks_store<T, K>(out, wb * K, a.n, part_pos(c0, wb, K), part_pos(c1, wb, K), lds, fin);
         raise_if_nonfinite(a.status, fin);
         if (!more)
             break;
@@ -523,7 +605,7 @@ __global__ __launch_bounds__(kWave) void sdc_persistent_kernel(TileArgs a, int n
     }
 }
 
-template <typename T, int K>
+template <typename T, int K, int NW>
 hipError_t launch_persistent_sdc(const TileArgs &a, hipStream_t stream)
 {
     static int per_cu = 0, ncu = 0;
@@ -531,8 +613,8 @@ hipError_t launch_persistent_sdc(const TileArgs &a, hipStream_t stream)
         int dev = 0, nb = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sdc_persistent_kernel<T, K>, kWave,
-                                                         0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sdc_persistent_kernel<T, K, NW>,
+                                                         NW * kWave, 0) != hipSuccess ||
             nb < 1 || ncu < 1)
             return hipErrorInvalidValue;
         per_cu = nb;
@@ -543,27 +625,40 @@ hipError_t launch_persistent_sdc(const TileArgs &a, hipStream_t stream)
     const int64_t rounds = (a.ntiles + cap - 1) / cap;
     int64_t nwg = (a.ntiles + rounds - 1) / rounds;
     nwg = (nwg + 7) / 8 * 8;
-    hipLaunchKernelGGL((sdc_persistent_kernel<T, K>), dim3((unsigned)nwg), dim3(kWave), 0, stream,
-                       a, (int)nwg);
+    hipLaunchKernelGGL((sdc_persistent_kernel<T, K, NW>), dim3((unsigned)nwg), dim3(NW * kWave), 0,
+                       stream, a, (int)nwg);
+    return hipGetLastError();
+}
+
+template <typename T, int K, int NW>
+hipError_t launch_one_sdc(const TileArgs &a, hipStream_t stream)
+{
+    const int64_t grid = (a.ntiles + 7) / 8 * 8;
+    hipLaunchKernelGGL((sdc_tile_kernel<T, K, NW>), dim3((unsigned)grid), dim3(NW * kWave), 0,
+                       stream, a);
     return hipGetLastError();
 }
 
 template <typename T, int K>
-hipError_t launch_one_sdc(const TileArgs &a, hipStream_t stream)
+hipError_t launch_sdc_nw(int nw, bool persistent, const TileArgs &a, hipStream_t stream)
 {
-    const int64_t grid = (a.ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((sdc_tile_kernel<T, K>), dim3((unsigned)grid), dim3(kWave), 0, stream, a);
-    return hipGetLastError();
+    switch (nw) {
+    case 1: return persistent ? launch_persistent_sdc<T, K, 1>(a, stream) : launch_one_sdc<T, K, 1>(a, stream);
+    case 2: return persistent ? launch_persistent_sdc<T, K, 2>(a, stream) : launch_one_sdc<T, K, 2>(a, stream);
+    case 4: return persistent ? launch_persistent_sdc<T, K, 4>(a, stream) : launch_one_sdc<T, K, 4>(a, stream);
+    case 8: return persistent ? launch_persistent_sdc<T, K, 8>(a, stream) : launch_one_sdc<T, K, 8>(a, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
-hipError_t launch_sdc_t(int k, bool persistent, const TileArgs &a, hipStream_t stream)
+hipError_t launch_sdc_t(int k, int nw, bool persistent, const TileArgs &a, hipStream_t stream)
 {
     switch (k) {
-    case 2: return persistent ? launch_persistent_sdc<T, 4>(a, stream) : launch_one_sdc<T, 4>(a, stream);
-    case 4: return persistent ? launch_persistent_sdc<T, 8>(a, stream) : launch_one_sdc<T, 8>(a, stream);
-    case 8: return persistent ? launch_persistent_sdc<T, 16>(a, stream) : launch_one_sdc<T, 16>(a, stream);
-    case 16: return persistent ? launch_persistent_sdc<T, 32>(a, stream) : launch_one_sdc<T, 32>(a, stream);
+    case 2: return launch_sdc_nw<T, 4>(nw, persistent, a, stream);
+    case 4: return launch_sdc_nw<T, 8>(nw, persistent, a, stream);
+    case 8: return launch_sdc_nw<T, 16>(nw, persistent, a, stream);
+    case 16: return launch_sdc_nw<T, 32>(nw, persistent, a, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -575,19 +670,21 @@ bool sdc_supported(int prec, int k)
     return (prec == kFP64 || prec == kFP32) && (k == 2 || k == 4 || k == 8 || k == 16);
 }
 
-hipError_t launch_sdc(int prec, int k, const TileArgs &a, hipStream_t stream)
+bool sdc_waves_supported(int nw) { return nw == 1 || nw == 2 || nw == 4 || nw == 8; }
+
+hipError_t launch_sdc(int prec, int k, int nw, const TileArgs &a, hipStream_t stream)
 {
-    if (prec == kFP64) return launch_sdc_t<double>(k, false, a, stream);
-    if (prec == kFP32) return launch_sdc_t<float>(k, false, a, stream);
+    if (prec == kFP64) return launch_sdc_t<double>(k, nw, false, a, stream);
+    if (prec == kFP32) return launch_sdc_t<float>(k, nw, false, a, stream);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sdc_persistent(int prec, int k, const TileArgs &a, hipStream_t stream)
+hipError_t launch_sdc_persistent(int prec, int k, int nw, const TileArgs &a, hipStream_t stream)
 {
     if (a.ntiles < 3 || a.in == a.out || a.nlev > kSdcMaxLevels)
         return hipErrorInvalidValue;
-    if (prec == kFP64) return launch_sdc_t<double>(k, true, a, stream);
-    if (prec == kFP32) return launch_sdc_t<float>(k, true, a, stream);
+    if (prec == kFP64) return launch_sdc_t<double>(k, nw, true, a, stream);
+    if (prec == kFP32) return launch_sdc_t<float>(k, nw, true, a, stream);
     return hipErrorInvalidValue;
 }
 

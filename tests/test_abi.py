@@ -289,7 +289,10 @@ def test_default_tile_follows_depth_and_source(prec, depth, src, want):
     (dict(n=31, k=4, precision=2), ge.GE_ERR_UNSUPPORTED),
     (dict(n=31, k=4, src_b=ctypes.c_void_p(0x1000)), ge.GE_ERR_UNSUPPORTED),
     (dict(n=31, k=4, tile=16), ge.GE_ERR_INVALID),
-    (dict(n=31, k=4, waves=4), ge.GE_ERR_INVALID),
+    (dict(n=31, k=4, waves=3), ge.GE_ERR_INVALID),
+    (dict(n=31, k=4, waves=16), ge.GE_ERR_INVALID),
+    (dict(n=32 * 1000 - 1, k=16, depth=46, waves=1), ge.GE_ERR_INVALID),   # halo 25 of 64
+    (dict(n=32 * 1000 - 1, k=16, depth=230, waves=4), ge.GE_ERR_INVALID),  # halo 123 of 256
     (dict(n=32 * 1000 - 1, k=16, depth=60), ge.GE_ERR_INVALID),   # halo wider than the window allows
     (dict(n=31, k=4, schedule=3), ge.GE_ERR_INVALID),
 ])
@@ -297,6 +300,19 @@ def test_subdomain_plan_rejects(kw, status):
     st, h = _plan(**kw)
     assert st == status, ge.last_error()
     assert not h.value
+
+
+def test_subdomain_wide_windows():
+    """Windows of 2 or 4 waves keep the halo per side of a single-wave window
+    (it depends on the depth only), so deeper launches fit."""
+    for waves, depth, halo in ((2, 46, 25), (4, 60, 32), (4, 24, 13)):
+        st, h = _plan(n=32 * 1000 - 1, k=16, depth=depth, waves=waves)
+        assert st == ge.GE_OK, ge.last_error()
+        t, d, w, hal = (ctypes.c_int32() for _ in range(4))
+        ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w),
+                                ctypes.byref(hal))
+        assert (t.value, d.value, w.value, hal.value) == (32, depth, waves, 32 * halo)
+        ge.lib().ge_destroy(h)
 
 
 def test_subdomain_plan_config():
@@ -316,9 +332,9 @@ def test_subdomain_plan_config():
 
 
 @pytest.mark.parametrize("n,schedule,want", [
-    (32 * 1000 - 1, 2, 2),      # 24 tiles of 42 couples: persistent as asked
+    (32 * 1000 - 1, 2, 2),      # 27 tiles of 38 couples (24 levels): persistent as asked
     (32 * 100 - 1, 2, 2),       # 3 tiles
-    (32 * 80 - 1, 2, 1),        # 2 tiles: one workgroup per tile
+    (32 * 70 - 1, 2, 1),        # 2 tiles: one workgroup per tile
     (32 * 64 - 1, 2, 1),        # one window, advanced in place
     (32 * 1000 - 1, 1, 1),
 ])
@@ -329,17 +345,22 @@ def test_subdomain_schedule(n, schedule, want):
     ge.lib().ge_destroy(h)
 
 
-@pytest.mark.parametrize("prec,k,want", [
-    (0, 16, (24, 2)),          # FP64, couples of 32: persistent, 24 levels
-    (1, 16, (20, 1)),          # FP32
-    (0, 8, (20, 1)),
+@pytest.mark.parametrize("n,prec,k,want", [
+    ((1 << 24) - 1, 0, 16, (4, 40, 2)),   # FP64, couples of 32: four waves, persistent
+    ((1 << 24) - 1, 1, 16, (8, 48, 1)),   # FP32: eight waves per tile
+    ((1 << 24) - 1, 0, 8, (8, 48, 1)),
+    ((1 << 24) - 1, 1, 2, (8, 48, 1)),
+    (262655, 0, 16, (1, 24, 2)),          # 8208 couples: too few for wide windows
+    (262655, 1, 16, (1, 20, 1)),
+    (32 * 400000 - 1, 0, 16, (1, 24, 2)),  # 1887 four-wave tiles: 7548 waves
+    (32 * 450000 - 1, 0, 16, (4, 40, 2)),  # 2123 tiles of 212 couples: 8492 waves
 ])
-def test_subdomain_library_choice(prec, k, want):
-    st, h = _plan(n=(1 << 24) - 1, k=k, precision=prec)
+def test_subdomain_library_choice(n, prec, k, want):
+    st, h = _plan(n=n, k=k, precision=prec)
     assert st == ge.GE_OK
     t, d, w, hal = (ctypes.c_int32() for _ in range(4))
     ge.lib().ge_plan_config(h, ctypes.byref(t), ctypes.byref(d), ctypes.byref(w), ctypes.byref(hal))
-    assert (d.value, ge.lib().ge_plan_schedule(h)) == want
+    assert (w.value, d.value, ge.lib().ge_plan_schedule(h)) == want
     ge.lib().ge_destroy(h)
 
 

@@ -28,11 +28,13 @@ def rel_l2(x, y):
     return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
 
 
-def run(u0, r, k, nsteps, precision="fp64", step0=0, gl=0.0, gr=0.0, depth=0, schedule=0):
+def run(u0, r, k, nsteps, precision="fp64", step0=0, gl=0.0, gr=0.0, depth=0, schedule=0,
+        waves=0):
     n = len(u0)
     scalar_l, scalar_r = np.ndim(gl) == 0, np.ndim(gr) == 0
     plan = ge.Plan(n, r, precision, g_left=gl if scalar_l else 0.0,
-                   g_right=gr if scalar_r else 0.0, depth=depth, k=k, schedule=schedule)
+                   g_right=gr if scalar_r else 0.0, depth=depth, k=k, schedule=schedule,
+                   waves=waves)
     u = ge.pack_state(u0, precision)
     d = lambda a: torch.from_numpy(np.asarray(a, dtype=np.float64)).cuda()
     plan.step_n(u, step0, nsteps, g_left_t=None if scalar_l else d(gl),
@@ -150,3 +152,51 @@ def test_persistent_schedule_time_dependent_walls():
     assert rel_l2(got, want) < 1e-12
     ref, _ = run(u0, 3.0, k, s, step0=3, gl=gl, gr=gr, schedule=1)
     np.testing.assert_array_equal(got, ref)
+
+
+# Windows of two, four or eight waves exchange their edge lanes' values
+# through LDS once per level; every value is still computed by the same
+# operations as in a single-wave window (the halo per side is the same), so
+# the bits agree.
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("k", [2, 4, 8, 16])
+@pytest.mark.parametrize("waves,schedule", [(2, 1), (4, 1), (8, 1), (2, 2), (4, 2), (8, 2)])
+def test_wave_counts_give_the_same_bits(k, precision, waves, schedule):
+    n = 2 * k * (64 * 4 * 37 + 19) - 1
+    u0 = rough(n, 70 + k)
+    ref, c1 = run(u0, 1.9, k, 45, precision=precision, gl=0.2, gr=-0.6, schedule=1, waves=1,
+                  depth=20)
+    got, c2 = run(u0, 1.9, k, 45, precision=precision, gl=0.2, gr=-0.6, schedule=schedule,
+                  waves=waves, depth=20)
+    assert (c1["waves"], c2["waves"], c2["schedule"]) == (1, waves, schedule)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("k", [2, 16])
+@pytest.mark.parametrize("couples", [3, 200, 256, 257, 256 * 3 + 41, 4000])
+@pytest.mark.parametrize("step0", [0, 1])
+def test_four_wave_windows_match_the_oracle(k, couples, step0):
+    """Single four-wave windows (up to 256 couples, advanced in place), a
+    window and a ragged second one, and many tiles, per tile and (from three
+    tiles on) persistent, against the oracle."""
+    n = 2 * k * couples - 1
+    u0 = rough(n, couples + 3 * k)
+    want = oracle.sdc_step_n(u0, 2.3, k, 33, step0=step0, gl=0.4, gr=-0.25)
+    got, cfg = run(u0, 2.3, k, 33, step0=step0, gl=0.4, gr=-0.25, waves=4, schedule=1)
+    assert cfg["waves"] == 4
+    assert rel_l2(got, want) < 1e-12, cfg
+    got2, cfg2 = run(u0, 2.3, k, 33, step0=step0, gl=0.4, gr=-0.25, waves=4, schedule=2)
+    np.testing.assert_array_equal(got2, got, err_msg=str(cfg2))
+
+
+def test_four_wave_windows_time_dependent_walls():
+    k, n, s = 16, 32 * 3000 - 1, 70
+    rng = np.random.default_rng(19)
+    u0 = rough(n, 19)
+    gl = np.cos(np.linspace(0, 2, s + 1))
+    gr = rng.uniform(-1, 1, s + 1)
+    want = oracle.sdc_step_n(u0, 3.0, k, s, step0=3, gl=gl, gr=gr)
+    for sched in (1, 2):
+        got, cfg = run(u0, 3.0, k, s, step0=3, gl=gl, gr=gr, schedule=sched, waves=4)
+        assert (cfg["waves"], cfg["schedule"]) == (4, sched)
+        assert rel_l2(got, want) < 1e-12

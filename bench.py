@@ -284,7 +284,7 @@ def paper_e2_table(torch, stream, ge, inputs):
     return out
 
 
-def grid2d_extra(torch, stream, ge, inputs, nx=4096, ny=4096, levels=200, depth=2):
+def grid2d_extra(torch, stream, ge, inputs, nx=4096, ny=4096, levels=200, depth=4):
     """The 2D extension on an nx x ny grid (u0 = sine rod profiles in x times
     a sine in y, seed 2), `depth` levels per launch (the library's choice):
     updates/s and the kernel against HBM bandwidth (one read and one write of

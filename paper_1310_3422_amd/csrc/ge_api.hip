@@ -182,8 +182,8 @@ struct ge_plan_s {
     double c1, c2, cs, e1, e2, es, tau, h;
     ge::StatusWords status;   // word 0: a launch stored a NaN or infinite value
     bool launched;            // a kernel may hold the status pointer
-    ge::SideStream side;      // wall kernel of split launches (created on first use)
-    int side_state;           // 0 not tried, 1 created, -1 creation failed
+    ge::SideStream side;      // wall kernel of split launches (side_state 1)
+    int side_state;           // 1 created, else none
 };
 
 namespace {
@@ -192,6 +192,22 @@ namespace {
 // Fewest tiles at which a plan keeps a second stream for split launches
 // (the split itself starts at 128 interior tiles per compute unit).
 constexpr int64_t kSideStreamTiles = 128 * 64;
+
+bool side_create(ge::SideStream &ss)
+{
+    bool ok = false;
+    if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) == hipSuccess) {
+        if (hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess) {
+            if (hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) == hipSuccess)
+                ok = true;
+            else
+                (void)hipEventDestroy(ss.fork);
+        }
+        if (!ok) (void)hipStreamDestroy(ss.stream);
+    }
+    (void)hipGetLastError();
+    return ok;
+}
 
 // The persistent form pays where one couple fills 32 FP64 registers per
 // node pair (k = 16): two waves per SIMD, so the per-tile form leaves its
@@ -447,6 +463,13 @@ ge_status ge_plan(ge_plan_t *out, const ge_desc *d)
     p->e2 = p->tau * r / (1.0 + 2.0 * r);
     p->es = p->tau / (1.0 + r);
     (void)ge::status_alloc(p->status);
+    // Per-tile launches over many tiles may split off their wall tiles: a
+    // second stream (default priority) lets the wall kernel run beside the
+    // interior one; without it (not created) they run one after the other.
+    // Made here, not at the first step, so that a step can be captured into
+    // a graph.
+    if (!p->persistent && !p->single && p->ntiles >= kSideStreamTiles)
+        p->side_state = side_create(p->side) ? 1 : -1;
     *out = p;
     return GE_OK;
 }
@@ -550,27 +573,8 @@ ge_status ge_step_n(ge_plan_t plan, void *u, void *workspace, int64_t step0, int
         a.nsdc = (plan->n + 1) / plan->tile;
         a.ca = plan->e1;
     }
-    // per-tile launches over many tiles may split off their wall tiles: give
-    // them a second stream (default priority) so that the wall kernel runs
-    // beside the interior one; without it they run one after the other
-    const ge::SideStream *side = nullptr;
-    if (!plan->sdc && !plan->persistent && !plan->single && plan->ntiles >= kSideStreamTiles) {
-        if (plan->side_state == 0) {
-            ge::SideStream &ss = plan->side;
-            plan->side_state = -1;
-            if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) == hipSuccess) {
-                if (hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess) {
-                    if (hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) == hipSuccess)
-                        plan->side_state = 1;
-                    else
-                        (void)hipEventDestroy(ss.fork);
-                }
-                if (plan->side_state != 1) (void)hipStreamDestroy(ss.stream);
-            }
-            (void)hipGetLastError();
-        }
-        if (plan->side_state == 1) side = &plan->side;
-    }
+    // the plan's second stream for split launches, if it holds one
+    const ge::SideStream *side = plan->side_state == 1 ? &plan->side : nullptr;
     // one launch of whichever kernel the plan runs
     auto launch = [&](const ge::TileArgs &la) {
         if (plan->sdc)

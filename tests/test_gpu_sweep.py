@@ -340,3 +340,36 @@ def test_source_tiles_bitwise(tile, waves, depth):
                         src_a=w.src_a, flux=True, tile=tile, waves=waves, depth=depth)
     np.testing.assert_array_equal(got, ref)
     np.testing.assert_array_equal(fgot, fref)
+
+
+def test_split_launch_captured_in_a_graph():
+    """A plan whose launches split off their wall tiles (the wall kernel on
+    the plan's second stream, forked from and joined back into the caller's
+    stream) can be captured: every replay equals an eager call, with eager
+    work and synchronisations between the replays."""
+    n, s = (1 << 23) + 5, 6
+    u0 = inputs.sine_rod(n, 7) + 0.05 * np.random.default_rng(11).standard_normal(n)
+    plan = ge.Plan(n, 3.0, "fp64", g_left=0.2, g_right=-0.1, tile=2, waves=1, depth=1, schedule=1)
+    ws = plan.new_workspace()
+    ref = ge.pack_state(u0, "fp64")
+    plan.step_n(ref, 0, s, workspace=ws)            # eager warm-up, and the first reference
+    torch.cuda.synchronize()
+    u = ge.pack_state(u0, "fp64")
+    g = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            plan.step_n(u, 0, s, workspace=ws)
+    torch.cuda.synchronize()
+    u.copy_(ge.pack_state(u0, "fp64"))
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, ref), f"replay {rep}"
+        # eager work between replays: the next reference, from the same state
+        nxt = ref.clone()
+        plan.step_n(nxt, 0, s, workspace=ws)
+        torch.cuda.synchronize()
+        ref = nxt

@@ -317,7 +317,8 @@ ge_status plan_sdc(ge_plan_t *out, const ge_desc *d)
     p->core = single ? nsdc : wsdc - 2 * halo;
     p->ntiles = (nsdc + p->core - 1) / p->core;
     p->persistent = !single && p->ntiles >= 3 &&
-                    (d->schedule == 2 || (auto_persistent && p->ntiles >= kSdcPersistentMinTiles));
+                    (d->schedule == 2 || (auto_persistent && p->ntiles >= kSdcPersistentMinTiles &&
+                                          depth <= ge::kSdcMaxLevels));
     const double r = d->r;
     p->h = 1.0 / (double)(p->n + 1);
     p->tau = r * p->h * p->h;

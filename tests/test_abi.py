@@ -302,6 +302,16 @@ def test_subdomain_plan_rejects(kw, status):
     assert not h.value
 
 
+def test_subdomain_deep_launches_stay_per_tile():
+    """The library takes the persistent sub-domain form only up to the 64
+    levels per launch it holds; deeper launches run one workgroup per tile."""
+    for depth, sched in ((64, 2), (80, 1)):
+        st, h = _plan(n=(1 << 24) - 1, k=16, depth=depth, waves=8)
+        assert st == ge.GE_OK, ge.last_error()
+        assert ge.lib().ge_plan_schedule(h) == sched
+        ge.lib().ge_destroy(h)
+
+
 def test_subdomain_wide_windows():
     """Windows of 2 or 4 waves keep the halo per side of a single-wave window
     (it depends on the depth only), so deeper launches fit."""

@@ -137,3 +137,15 @@ def test_depths_give_the_same_bits(precision, nx, ny, nsteps):
     if precision == "fp64":
         want = oracle.step2d_n(u0, 1.4, 2.6, nsteps, step0=3, walls=WALLS)
         assert rel_l2(outs[0].astype(np.float64), want) < 1e-12
+
+
+def test_fp32_interior_tiles_four_levels_per_launch():
+    """A grid large enough for tiles that touch no wall (the path without
+    per-point tests), FP32 at four levels per launch, against the oracle."""
+    nx, ny = 700, 300
+    u0 = grid(nx, ny, 29)
+    v0 = u0.astype(np.float32).astype(np.float64)
+    w = tuple(float(np.float32(g)) for g in WALLS)
+    got = run(u0, 1.3, 2.1, 12, step0=1, walls=WALLS, precision="fp32")
+    want = oracle.step2d_n(v0, 1.3, 2.1, 12, step0=1, walls=w)
+    assert rel_l2(got, want) < 1e-5

@@ -200,3 +200,25 @@ def test_four_wave_windows_time_dependent_walls():
         got, cfg = run(u0, 3.0, k, s, step0=3, gl=gl, gr=gr, schedule=sched, waves=4)
         assert (cfg["waves"], cfg["schedule"]) == (4, sched)
         assert rel_l2(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("k", [4, 16])
+def test_wide_windows_fp32_time_dependent_walls(k):
+    """FP32 in windows of eight waves (the library's FP32 choice on long
+    rods), per tile and persistent, with walls that change every level,
+    against the oracle started from the same FP32-rounded values."""
+    n, s = 2 * k * 9000 - 1, 61
+    rng = np.random.default_rng(23)
+    u0 = rough(n, 23)
+    v0 = ge.unpack_state(ge.pack_state(u0, "fp32"), n, "fp32")
+    gl = np.sin(np.linspace(0, 2.5, s + 1)).astype(np.float32).astype(np.float64)
+    gr = rng.uniform(-1, 1, s + 1).astype(np.float32).astype(np.float64)
+    want = oracle.sdc_step_n(v0, 2.6, k, s, step0=1, gl=gl, gr=gr)
+    outs = []
+    for sched in (1, 2):
+        got, cfg = run(u0, 2.6, k, s, precision="fp32", step0=1, gl=gl, gr=gr, schedule=sched,
+                       waves=8, depth=24)
+        assert (cfg["waves"], cfg["schedule"]) == (8, sched)
+        assert rel_l2(got, want) < 1e-5, cfg
+        outs.append(got)
+    np.testing.assert_array_equal(outs[1], outs[0])

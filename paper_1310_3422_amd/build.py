@@ -2,6 +2,7 @@
 import glob
 import os
 import subprocess
+import time
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -20,8 +21,16 @@ HIP_FLAGS = [
 ]
 
 
+# the longest compiles (many kernel instantiations) start first
+_SLOW_FIRST = ("ge_sweep_fp64_wide.hip", "ge_sweep_fp64_mid.hip", "ge_batch.hip",
+               "ge_sweep_fp32.hip", "ge_sweep.hip", "ge_sweep_fp64_narrow.hip", "ge_2d.hip")
+
+
 def sources():
-    return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
+    def rank(path):
+        name = os.path.basename(path)
+        return (_SLOW_FIRST.index(name) if name in _SLOW_FIRST else len(_SLOW_FIRST), name)
+    return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")), key=rank)
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
@@ -36,10 +45,16 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         cmd = [HIPCC, *HIP_FLAGS, *inc, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
+        while len(procs) >= jobs:          # wait for any compile to finish
+            for p in procs:
+                if p.poll() is not None:
+                    if p.returncode != 0:
+                        raise RuntimeError("hipcc failed")
+                    procs.remove(p)
+                    break
+            else:
+                time.sleep(0.2)
         procs.append(subprocess.Popen(cmd))
-        if len(procs) >= jobs:
-            if procs.pop(0).wait() != 0:
-                raise RuntimeError("hipcc failed")
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")

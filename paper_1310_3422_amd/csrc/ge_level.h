@@ -1,5 +1,5 @@
 // One level of the GE sweep on a register tile, shared by the single-rod
-// tile kernel (ge_sweep.hip) and the persistent batch kernel (ge_batch.hip).
+// tile kernel (ge_sweep_kernels.h) and the persistent batch kernel (ge_batch.hip).
 //
 // Scheme (Section 2, two-point groups): at level m with p = m mod 2 the
 // points are coupled as (0,1),(2,3),... (0-based) when p = 0 and

@@ -1,5 +1,5 @@
 // One window of the tiled GE sweep (Section 2, two-point groups), shared by
-// the single-rod kernels (ge_sweep.hip) and the multi-pass tasks of the
+// the single-rod kernels (ge_sweep_kernels.h) and the multi-pass tasks of the
 // batch kernel (ge_batch.hip).
 //
 // A window of W = NW*64*K consecutive points starts at ws; thread `tid`

@@ -149,3 +149,20 @@ def test_fp32_interior_tiles_four_levels_per_launch():
     got = run(u0, 1.3, 2.1, 12, step0=1, walls=WALLS, precision="fp32")
     want = oracle.step2d_n(v0, 1.3, 2.1, 12, step0=1, walls=w)
     assert rel_l2(got, want) < 1e-5
+
+
+def test_large_grid_every_depth():
+    """A grid of thousands of tiles per launch (most of them touching no
+    wall): every depth gives the same bits, and they match the oracle."""
+    nx, ny = 4096, 2048
+    u0 = grid(nx, ny, 31)
+    want = oracle.step2d_n(u0, 1.9, 0.7, 9, step0=1, walls=WALLS)
+    outs = []
+    for depth in (1, 2, 4):
+        u = torch.from_numpy(u0.copy()).cuda()
+        ge.step2d_n(u, nx, ny, 1.9, 0.7, 1, 9, walls=WALLS, depth=depth)
+        torch.cuda.synchronize()
+        outs.append(u.cpu().numpy())
+    np.testing.assert_array_equal(outs[1], outs[0])
+    np.testing.assert_array_equal(outs[2], outs[0])
+    assert rel_l2(outs[0], want) < 1e-12

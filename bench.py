@@ -77,8 +77,8 @@ BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak, published
 NN_FLOPS_PER_POINT = 2 * 5 * (2 * 64 + 4 * 64 * 64 + 64 * 1)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1310_3422_amd", "csrc", f)
                   for f in ("ge_sweep_kernels.h", "ge_sweep.hip", "ge_sweep_fp64_narrow.hip",
-                            "ge_sweep_fp64_wide.hip", "ge_sweep_fp32.hip", "ge_tile.h",
-                            "ge_level.h", "ge_kernels.h")]
+                            "ge_sweep_fp64_mid.hip", "ge_sweep_fp64_wide.hip",
+                            "ge_sweep_fp32.hip", "ge_tile.h", "ge_level.h", "ge_kernels.h")]
 
 
 def kernel_source_hash():

@@ -100,11 +100,12 @@ def test_forward_matches_oracle(width, batch):
     assert rel_l2(got, exact) < 20 * BF16_FLIP_TOL
 
 
-@pytest.mark.parametrize("width,batch", [(640, 2), (4096, 3)])
+@pytest.mark.parametrize("width,batch", [(128, 2), (384, 1), (640, 2), (896, 2), (4096, 3)])
 def test_fused_jump_is_the_layered_forward_plus_the_scaled_increment(width, batch):
     """The six-layer fused jump gives the bits of the layer-by-layer forward
-    pass combined as u + (64 r s) out in FP32, in place or not (512 points:
-    a full and a ragged tile of the fused kernel at 640)."""
+    pass combined as u + (64 r s) out in FP32, in place or not.  The fused
+    kernel takes 512-point tiles: 128 and 384 are one ragged tile, 640 and
+    896 a full and a ragged one, 4096 eight full ones."""
     params = fp32_params(8)
     r, u, _ = rods(41, batch, width, levels=0)
     net = make_net(width, batch, params)
